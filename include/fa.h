@@ -1,0 +1,226 @@
+/*
+ * fa.h -- C ABI of the MI355X (gfx950) micro-model decode/query library.
+ *
+ * A micro-model (paper Sec. 4.2, Eq. 2 and the micro-model layout figure)
+ * is a clamped tensor-product B-spline over one micro-block: three knot
+ * vectors plus an NCP_x x NCP_y x NCP_z lattice of control points.  The
+ * renderer of Alg. 4 queries it through valueMicroModel(x,y,z) and
+ * gradientMicroModel(x,y,z); this library evaluates both, for whole
+ * batches of micro-models of uneven NCP* (Sec. 4.2.1, Eq. 4), either on a
+ * voxel grid per block (fa_decode_blocks) or at arbitrary sample positions
+ * of a tiled domain (fa_query_points), and provides the adjoint of the grid
+ * decode (fa_decode_backward), i.e. the gradient of a least-squares fit of
+ * the control points (the fit that Alg. 1 runs for every candidate NCP).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Parameter domain of a block: [0,1]^3.  Knots are clamped: the first
+ *    p+1 knots of an axis are 0, the last p+1 are 1, interior knots are
+ *    non-decreasing, and every knot span used has positive length.
+ *  - Span rule: the span of u is the largest s in [p, n-1] with t_s <= u;
+ *    u = 1 belongs to the last span (n-1).
+ *  - Lattice layout: C order [x][y][z] (z fastest); element (i,j,k) of
+ *    block b is ctrl[ctrl_off + (i*ncp_y + j)*ncp_z + k].
+ *  - Knot layout: knots[knot_off ...] holds the x knots (ncp_x+p+1 values),
+ *    then the y knots, then the z knots, FP32.
+ *  - Decode grid: voxel i of an axis of resolution R sits at the FP32
+ *    value (float)i / (float)(R-1) (end points included, so neighbouring
+ *    blocks that share a boundary sample -- Sec. 4.2 -- decode it twice).
+ *  - Channel mask: bit 0 value, bit 1 d/du (x), bit 2 d/dv (y), bit 3
+ *    d/dw (z).  Outputs hold only the selected channels, in that order.
+ *  - Pointers documented "device" must be device memory of the current
+ *    HIP device; "host" pointers are read synchronously and may be freed
+ *    on return.  The caller owns every buffer; no hot call allocates.
+ *  - `stream` is a hipStream_t (0 = the null stream).  Hot calls are
+ *    asynchronous on it, never synchronise, and may be captured into a
+ *    HIP graph.  Argument errors are returned before anything is launched
+ *    and leave every output untouched.
+ */
+#ifndef FA_H
+#define FA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fa_status {
+    FA_OK = 0,
+    FA_ERR_INVALID_ARG = 1, /* null pointer, bad size, malformed descriptor */
+    FA_ERR_UNSUPPORTED = 2, /* valid B-spline outside what the kernels take */
+    FA_ERR_DEVICE = 3       /* a HIP call or launch failed */
+} fa_status;
+
+typedef enum fa_dtype {
+    FA_F32 = 0,  /* control points stored as float                         */
+    FA_BF16 = 1, /* bfloat16 holding P / scale (per-block max-abs scaling) */
+    FA_F16 = 2   /* IEEE half holding P / scale                             */
+} fa_dtype;
+
+/* Maximum degree and control points per axis taken by the kernels. */
+#define FA_MAX_DEGREE 3
+#define FA_MAX_NCP 64
+#define FA_MAX_RES 256
+
+/* Descriptor flag bits written by fa_validate_blocks. */
+#define FA_FLAG_UNIFORM_X 1u /* x knots are exactly (float)(j-p)/(float)(n-p) */
+#define FA_FLAG_UNIFORM_Y 2u
+#define FA_FLAG_UNIFORM_Z 4u
+
+/* One micro-model (64 bytes).  ncp[a] >= degree[a]+1 and <= FA_MAX_NCP;
+ * the three degrees must be equal (a micro-model has one degree, Eq. 2)
+ * and lie in [1, FA_MAX_DEGREE].  scale multiplies every stored control
+ * point of a BF16/FP16 lattice; FP32 lattices ignore it. */
+typedef struct fa_block {
+    int32_t ncp[3];
+    int32_t degree[3];
+    int64_t knot_off; /* element offset into the knot array          */
+    int64_t ctrl_off; /* element offset into the lattice array; a
+                         multiple of 4 elements                       */
+    float scale;
+    uint32_t flags;   /* FA_FLAG_* (set by fa_validate_blocks)        */
+    int32_t reserved[4];
+} fa_block;
+
+/* One unit of work of the batched decode: rows [row0, row0+nrows) of the
+ * y axis, z lanes [col0, col0+64), all x, of block `block`. */
+typedef struct fa_work {
+    int32_t block;
+    int16_t row0;
+    int16_t nrows;
+    int16_t col0;
+    int16_t pad;
+} fa_work;
+
+/* Tunables of the batched decode (a0: batch plan and persistent schedule).
+ * Zero fields take defaults. */
+typedef struct fa_tune {
+    int32_t rows_per_item; /* y rows per work item (multiple of waves)    */
+    int32_t waves;         /* waves (64 lanes) per workgroup, 1..16       */
+    int32_t grid;          /* persistent workgroups; 0 = one per item     */
+    int32_t kernel;        /* 0 = separable VALU, 1 = separable MFMA      */
+} fa_tune;
+
+const char *fa_status_string(fa_status s);
+
+/* Version of this ABI (major*10000 + minor*100 + patch). */
+int32_t fa_version(void);
+
+/*
+ * Check host copies of the descriptors and knots (Sec. 4.2 micro-model
+ * content) once, before any hot call, and set each descriptor's `flags`.
+ *   blocks  host, nblocks entries, read and written (flags only)
+ *   knots   host, nknots floats
+ *   nctrl   number of lattice elements the caller will pass
+ * Returns FA_ERR_INVALID_ARG for: null pointers, nblocks <= 0, ncp <
+ * degree+1, unequal degrees, offsets or lengths outside the arrays, knots
+ * that are not clamped on [0,1] or decrease; FA_ERR_UNSUPPORTED for degree
+ * > FA_MAX_DEGREE or ncp > FA_MAX_NCP.  Nothing is written on error.
+ */
+fa_status fa_validate_blocks(fa_block *blocks, int32_t nblocks, const float *knots,
+                             int64_t nknots, int64_t nctrl);
+
+/*
+ * Batch plan (row a0): split every block into work items and assign them
+ * to `grid` persistent workgroups by longest-processing-time-first on a
+ * per-item cost model (work of uneven NCP* and degree differs).
+ *   blocks  host descriptors (validated)
+ *   res     host, 3 ints in [2, FA_MAX_RES]
+ *   tune    host, may be NULL
+ *   work    host, capacity entries; receives the items grouped by
+ *           workgroup
+ *   wg_off  host, capacity+1 entries; workgroup g runs
+ *           work[wg_off[g] .. wg_off[g+1])
+ *   nwork, ngroups  receive the item and workgroup counts
+ * The item count is nblocks * ceil(res[1]/rows) * ceil(res[2]/64); a
+ * capacity below it returns FA_ERR_INVALID_ARG.
+ */
+fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t res[3],
+                         const fa_tune *tune, fa_work *work, int32_t *wg_off,
+                         int64_t capacity, int64_t *nwork, int32_t *ngroups);
+
+/*
+ * Decode every block on its res[0] x res[1] x res[2] grid: value and/or
+ * gradient with respect to the block parameters (Alg. 4, valueMicroModel
+ * and gradientMicroModel at every voxel) -- the batched, persistent form.
+ *   blocks  device, nblocks descriptors (validated on the host first)
+ *   knots   device FP32
+ *   ctrl    device lattice of `dtype` (FA_BF16/FA_F16 hold P/scale)
+ *   work, wg_off  device copies of a plan from fa_plan_decode made with
+ *           the same tune and res, or both NULL for the default order
+ *   ngroups workgroups in the plan (ignored when work is NULL)
+ *   out     device FP32 [nblocks][popcount(mask)][res0][res1][res2]
+ * FA_ERR_UNSUPPORTED if tune->kernel selects the MFMA kernel with a
+ * dtype or degree it does not take.
+ */
+fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
+                           const void *ctrl, fa_dtype dtype, const int32_t res[3],
+                           uint32_t mask, const fa_tune *tune, const fa_work *work,
+                           const int32_t *wg_off, int32_t ngroups, float *out,
+                           void *stream);
+
+/*
+ * The plain form of the same decode: one launch per block, one thread per
+ * voxel, each thread doing its own span search, basis evaluation and
+ * (p+1)^3 window sum.  Same arguments and output as fa_decode_blocks
+ * (FP32 lattices only).  It exists as the baseline the batched form is
+ * measured against.
+ */
+fa_status fa_decode_blocks_plain(const fa_block *blocks, int32_t nblocks,
+                                 const float *knots, const float *ctrl,
+                                 const int32_t res[3], uint32_t mask, float *out,
+                                 void *stream);
+
+/*
+ * Point query over a domain tiled by nb[0] x nb[1] x nb[2] cells (Alg. 4:
+ * getSampleLocation, then valueMicroModel and gradientMicroModel).
+ *   blocks, knots, ctrl, dtype   as for fa_decode_blocks
+ *   block_of_cell  device int32 [nb0][nb1][nb2]: descriptor index of each
+ *           cell; -1 (or any index outside [0, nblocks)) marks an empty
+ *           cell, whose samples return zeros
+ *   nb, origin, extent  host, 3 each; extent > 0
+ *   xyz     device FP32 [n][3]
+ *   out     device FP32 [n][4] = value, d/dx, d/dy, d/dz in domain units
+ *           (channels not in mask are written as 0)
+ * Block lookup in FP32, one rounding per operation:
+ *   r = (float)nb/extent;  q = clamp((x - origin)*r, 0, nb);
+ *   b = min(floor(q), nb-1);  u = q - b  (exact);  d/dx = r * d/du.
+ * Positions outside the domain are clamped onto it.
+ */
+fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
+                          const int32_t *block_of_cell, const int32_t nb[3],
+                          const float origin[3], const float extent[3], const float *knots,
+                          const void *ctrl, fa_dtype dtype, const float *xyz, int64_t n,
+                          uint32_t mask, float *out, void *stream);
+
+/*
+ * Adjoint of the grid decode (row a7): grad_ctrl = B^T grad_out, where B
+ * is the linear map ctrl -> decode output of fa_decode_blocks for the same
+ * blocks, res and mask.  Deterministic (no atomics).
+ *   grad_out   device FP32 [nblocks][popcount(mask)][res0][res1][res2]
+ *   grad_ctrl  device FP32 lattice layout (same offsets as ctrl); the
+ *              lattices of the blocks are overwritten, other elements are
+ *              left untouched
+ *   rows_per_item  x control planes owned per workgroup (0 = default)
+ */
+fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
+                             const int32_t res[3], uint32_t mask, const float *grad_out,
+                             float *grad_ctrl, int32_t rows_per_item, void *stream);
+
+/*
+ * Per-block max-abs scaling and rounding to BF16/FP16 (row a4): for each
+ * block, s_b = max |P_b| (1 when the lattice is all zeros), blocks[b].scale
+ * = s_b, and ctrl_lp = round-to-nearest-even(P_b / s_b).
+ *   blocks   device descriptors; `scale` is written
+ *   ctrl_f32 device FP32 lattices
+ *   ctrl_lp  device, 2-byte elements, same offsets
+ */
+fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctrl_f32,
+                             fa_dtype dtype, void *ctrl_lp, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FA_H */

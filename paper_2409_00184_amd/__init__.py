@@ -1,0 +1,288 @@
+"""MI355X (gfx950) micro-model decode and query: thin Python binding.
+
+Every computation runs in the HIP kernels of libfa.so (include/fa.h); this
+module only marshals arguments: torch tensors provide device memory and the
+current stream.  There is no CPU fallback: if libfa.so is missing, importing
+the binding raises.
+
+Entry points (same names as the C ABI):
+  fa_validate_blocks, fa_plan_decode, fa_decode_blocks,
+  fa_decode_blocks_plain, fa_query_points, fa_decode_backward,
+  fa_quantize_blocks
+and the conveniences MicroModels, Plan, decode, decode_plain, query,
+decode_backward, FADecode (torch.autograd.Function), capture.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+__all__ = ["FA_F32", "FA_BF16", "FA_F16", "BLOCK_DTYPE", "WORK_DTYPE", "FAError", "lib",
+           "MicroModels", "Plan", "decode", "decode_plain", "query", "decode_backward",
+           "FADecode", "capture", "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfa.so")
+
+FA_OK, FA_ERR_INVALID_ARG, FA_ERR_UNSUPPORTED, FA_ERR_DEVICE = 0, 1, 2, 3
+FA_F32, FA_BF16, FA_F16 = 0, 1, 2
+DTYPES = {"f32": FA_F32, "bf16": FA_BF16, "f16": FA_F16}
+
+BLOCK_DTYPE = np.dtype([("ncp", "<i4", (3,)), ("degree", "<i4", (3,)), ("knot_off", "<i8"),
+                        ("ctrl_off", "<i8"), ("scale", "<f4"), ("flags", "<u4"),
+                        ("reserved", "<i4", (4,))], align=True)
+assert BLOCK_DTYPE.itemsize == 64
+WORK_DTYPE = np.dtype([("block", "<i4"), ("row0", "<i2"), ("nrows", "<i2"), ("col0", "<i2"),
+                       ("pad", "<i2")])
+assert WORK_DTYPE.itemsize == 12
+
+
+class FATune(ctypes.Structure):
+    _fields_ = [("rows_per_item", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+
+
+class FAError(RuntimeError):
+    def __init__(self, call, status):
+        self.status = status
+        super().__init__(f"{call}: {lib.fa_status_string(status).decode()} (status {status})")
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()'); there is no CPU fallback")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.fa_status_string.restype = ctypes.c_char_p
+    L.fa_status_string.argtypes = [ctypes.c_int]
+    L.fa_version.restype = i32
+    L.fa_validate_blocks.restype = ctypes.c_int
+    L.fa_validate_blocks.argtypes = [vp, i32, vp, i64, i64]
+    L.fa_plan_decode.restype = ctypes.c_int
+    L.fa_plan_decode.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp, vp]
+    L.fa_decode_blocks.restype = ctypes.c_int
+    L.fa_decode_blocks.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, u32, vp, vp, vp, i32, vp,
+                                   vp]
+    L.fa_decode_blocks_plain.restype = ctypes.c_int
+    L.fa_decode_blocks_plain.argtypes = [vp, i32, vp, vp, vp, u32, vp, vp]
+    L.fa_query_points.restype = ctypes.c_int
+    L.fa_query_points.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, u32,
+                                  vp, vp]
+    L.fa_decode_backward.restype = ctypes.c_int
+    L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
+    L.fa_quantize_blocks.restype = ctypes.c_int
+    L.fa_quantize_blocks.argtypes = [vp, i32, vp, ctypes.c_int, vp, vp]
+    return L
+
+
+lib = _load()
+
+
+def _check(call, st):
+    if st != FA_OK:
+        raise FAError(call, st)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _i32x3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+def _f32x3(v):
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
+
+
+def nch(mask):
+    return bin(int(mask) & 15).count("1")
+
+
+def host_descriptors(ncp, deg, knot_off, ctrl_off):
+    d = np.zeros(len(ncp), BLOCK_DTYPE)
+    d["ncp"] = np.asarray(ncp, np.int32).reshape(-1, 3)
+    d["degree"] = np.asarray(deg, np.int32).reshape(-1, 3)
+    d["knot_off"] = np.asarray(knot_off, np.int64)
+    d["ctrl_off"] = np.asarray(ctrl_off, np.int64)
+    d["scale"] = 1.0
+    return d
+
+
+def fa_validate_blocks(desc, knots, nctrl):
+    """Host validation; sets desc['flags'] in place (C ABI fa_validate_blocks)."""
+    knots = np.ascontiguousarray(knots, np.float32)
+    st = lib.fa_validate_blocks(desc.ctypes.data, len(desc), knots.ctypes.data, knots.size,
+                                int(nctrl))
+    _check("fa_validate_blocks", st)
+    return desc
+
+
+class MicroModels:
+    """A batch of micro-models resident on the GPU.
+
+    Built from host arrays (ncp, degree, knot_off, ctrl_off, knots, ctrl);
+    validated by fa_validate_blocks, then copied to the device.  Low-precision
+    lattices are made on the device by fa_quantize_blocks (per-block max-abs
+    scale written into the device descriptors `desc_lp`).
+    """
+
+    def __init__(self, ncp, deg, knot_off, ctrl_off, knots, ctrl, device="cuda"):
+        ctrl = torch.as_tensor(ctrl, dtype=torch.float32)
+        self.host_desc = fa_validate_blocks(host_descriptors(ncp, deg, knot_off, ctrl_off),
+                                            knots, ctrl.numel())
+        self.nblocks = len(self.host_desc)
+        self.device = torch.device(device)
+        self.desc = torch.from_numpy(self.host_desc.view(np.uint8).copy()).to(self.device)
+        self.knots = torch.as_tensor(np.ascontiguousarray(knots, np.float32)).to(self.device)
+        self.ctrl = ctrl.to(self.device).contiguous()
+        self.ctrl_lp = {}
+        self.desc_lp = {}
+
+    @classmethod
+    def from_batch(cls, b, device="cuda"):
+        return cls(b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, b.ctrl, device)
+
+    def set_ctrl(self, ctrl):
+        """Replace the FP32 lattice (same layout); drops low-precision copies."""
+        assert ctrl.shape == self.ctrl.shape and ctrl.dtype == torch.float32
+        self.ctrl = ctrl.contiguous()
+        self.ctrl_lp.clear()
+        self.desc_lp.clear()
+
+    def lattice(self, dtype="f32", stream=None):
+        """(device descriptors, lattice) for a storage dtype."""
+        if dtype == "f32":
+            return self.desc, self.ctrl
+        if dtype not in self.ctrl_lp:
+            desc = self.desc.clone()
+            lp = torch.zeros(self.ctrl.numel(), dtype=torch.int16, device=self.device)
+            st = lib.fa_quantize_blocks(_ptr(desc), self.nblocks, _ptr(self.ctrl), DTYPES[dtype],
+                                        _ptr(lp), _stream(stream))
+            _check("fa_quantize_blocks", st)
+            self.desc_lp[dtype], self.ctrl_lp[dtype] = desc, lp
+        return self.desc_lp[dtype], self.ctrl_lp[dtype]
+
+
+class Plan:
+    """Host batch plan (fa_plan_decode) copied to the device."""
+
+    def __init__(self, models, res, rows=0, waves=0, grid=0, kernel=0):
+        self.tune = FATune(int(rows), int(waves), int(grid), int(kernel))
+        cap = models.nblocks * ((int(res[1]) + 0) * ((int(res[2]) + 63) // 64))
+        work = np.zeros(cap, WORK_DTYPE)
+        off = np.zeros(cap + 1, np.int32)
+        nwork = ctypes.c_int64(0)
+        ngroups = ctypes.c_int32(0)
+        st = lib.fa_plan_decode(models.host_desc.ctypes.data, models.nblocks, _i32x3(res),
+                                ctypes.byref(self.tune), work.ctypes.data, off.ctypes.data,
+                                cap, ctypes.byref(nwork), ctypes.byref(ngroups))
+        _check("fa_plan_decode", st)
+        self.nwork, self.ngroups = nwork.value, ngroups.value
+        self.host_work = work[:self.nwork].copy()
+        self.host_off = off[:self.ngroups + 1].copy()
+        self.work = torch.from_numpy(self.host_work.view(np.uint8).copy()).to(models.device)
+        self.wg_off = torch.from_numpy(self.host_off).to(models.device)
+        self.res = tuple(int(r) for r in res)
+
+
+def decode(models, res, mask=15, dtype="f32", plan=None, tune=None, out=None, stream=None):
+    """Batched grid decode (fa_decode_blocks) -> [nb, nch, R0, R1, R2] float32."""
+    desc, ctrl = models.lattice(dtype, stream)
+    if out is None:
+        out = torch.empty((models.nblocks, nch(mask)) + tuple(int(r) for r in res),
+                          dtype=torch.float32, device=models.device)
+    if plan is not None:
+        assert plan.res == tuple(int(r) for r in res)
+        t, work, off, ng = plan.tune, _ptr(plan.work), _ptr(plan.wg_off), plan.ngroups
+    else:
+        t = tune if tune is not None else FATune(0, 0, 0, 0)
+        work, off, ng = None, None, 0
+    st = lib.fa_decode_blocks(_ptr(desc), models.nblocks, _ptr(models.knots), _ptr(ctrl),
+                              DTYPES[dtype], _i32x3(res), int(mask), ctypes.byref(t), work, off,
+                              ng, _ptr(out), _stream(stream))
+    _check("fa_decode_blocks", st)
+    return out
+
+
+def decode_plain(models, res, mask=15, out=None, stream=None):
+    """Plain per-voxel decode, one launch per block (fa_decode_blocks_plain)."""
+    if out is None:
+        out = torch.empty((models.nblocks, nch(mask)) + tuple(int(r) for r in res),
+                          dtype=torch.float32, device=models.device)
+    st = lib.fa_decode_blocks_plain(_ptr(models.desc), models.nblocks, _ptr(models.knots),
+                                    _ptr(models.ctrl), _i32x3(res), int(mask), _ptr(out),
+                                    _stream(stream))
+    _check("fa_decode_blocks_plain", st)
+    return out
+
+
+def query(models, xyz, nb, origin, extent, block_of_cell, mask=15, dtype="f32", out=None,
+          stream=None):
+    """Point query (fa_query_points): xyz [n, 3] float32 -> [n, 4] float32."""
+    desc, ctrl = models.lattice(dtype, stream)
+    assert xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.shape[-1] == 3
+    n = xyz.numel() // 3
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=models.device)
+    st = lib.fa_query_points(_ptr(desc), models.nblocks, _ptr(block_of_cell), _i32x3(nb),
+                             _f32x3(origin), _f32x3(extent), _ptr(models.knots), _ptr(ctrl),
+                             DTYPES[dtype], _ptr(xyz), n, int(mask), _ptr(out),
+                             _stream(stream))
+    _check("fa_query_points", st)
+    return out
+
+
+def decode_backward(models, res, grad_out, mask=1, grad_ctrl=None, rows=0, stream=None):
+    """Adjoint B^T g (fa_decode_backward) -> lattice-layout float32."""
+    assert grad_out.dtype == torch.float32 and grad_out.is_contiguous()
+    if grad_ctrl is None:
+        grad_ctrl = torch.zeros_like(models.ctrl)
+    st = lib.fa_decode_backward(_ptr(models.desc), models.nblocks, _ptr(models.knots),
+                                _i32x3(res), int(mask), _ptr(grad_out), _ptr(grad_ctrl),
+                                int(rows), _stream(stream))
+    _check("fa_decode_backward", st)
+    return grad_ctrl
+
+
+class FADecode(torch.autograd.Function):
+    """value (and gradient channels) = B(ctrl); backward = B^T (HIP adjoint)."""
+
+    @staticmethod
+    def forward(ctx, ctrl, models, res, mask, plan):
+        models.set_ctrl(ctrl.detach())
+        out = decode(models, res, mask, plan=plan)
+        ctx.models, ctx.res, ctx.mask = models, res, mask
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        gc = decode_backward(ctx.models, ctx.res, g.contiguous(), ctx.mask)
+        return gc, None, None, None, None
+
+
+def capture(fn, warmup=1):
+    """Capture fn() (HIP calls on the current stream) into a graph; returns
+    (graph, result of the captured call)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        res = fn()
+    return g, res

@@ -1,0 +1,297 @@
+// C ABI of the micro-model decode/query library: argument checking,
+// descriptor validation, the batch planner (row a0) and the launches.
+// Every entry point is declared and documented in include/fa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+#include "../../include/fa.h"
+#include "fa_internal.hpp"
+
+using namespace fa;
+
+namespace {
+
+constexpr int kDefaultWaves = 4;
+constexpr int kDefaultRows = 8;
+constexpr int kDefaultGrid = 768;  // 256 CUs x 3 resident workgroups (LDS bound)
+
+int popcount4(uint32_t m) { return __builtin_popcount(m & 15u); }
+
+bool res_ok(const int32_t *res) {
+    if (!res) return false;
+    for (int a = 0; a < 3; ++a)
+        if (res[a] < 2) return false;
+    return true;
+}
+
+bool res_supported(const int32_t *res) {
+    for (int a = 0; a < 3; ++a)
+        if (res[a] > FA_MAX_RES) return false;
+    return true;
+}
+
+struct Tune {
+    int rows, waves, grid, kernel;
+};
+
+Tune resolve(const fa_tune *t) {
+    Tune r{kDefaultRows, kDefaultWaves, 0, 0};
+    if (t) {
+        if (t->rows_per_item > 0) r.rows = t->rows_per_item;
+        if (t->waves > 0) r.waves = t->waves;
+        if (t->grid > 0) r.grid = t->grid;
+        r.kernel = t->kernel;
+    }
+    return r;
+}
+
+bool waves_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
+}  // namespace
+
+extern "C" {
+
+const char *fa_status_string(fa_status s) {
+    switch (s) {
+    case FA_OK: return "ok";
+    case FA_ERR_INVALID_ARG: return "invalid argument";
+    case FA_ERR_UNSUPPORTED: return "unsupported";
+    case FA_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+int32_t fa_version(void) { return 10000; }
+
+fa_status fa_validate_blocks(fa_block *blocks, int32_t nblocks, const float *knots,
+                             int64_t nknots, int64_t nctrl) {
+    if (!blocks || !knots || nblocks <= 0 || nknots <= 0 || nctrl <= 0)
+        return FA_ERR_INVALID_ARG;
+    std::vector<uint32_t> flags(nblocks, 0u);
+    fa_status worst = FA_OK;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const fa_block &B = blocks[b];
+        const int p = B.degree[0];
+        if (B.degree[1] != p || B.degree[2] != p || p < 1) return FA_ERR_INVALID_ARG;
+        if (p > FA_MAX_DEGREE) worst = FA_ERR_UNSUPPORTED;
+        int64_t klen = 0, clen = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (B.ncp[a] < p + 1) return FA_ERR_INVALID_ARG;
+            if (B.ncp[a] > FA_MAX_NCP) worst = FA_ERR_UNSUPPORTED;
+            klen += B.ncp[a] + p + 1;
+            clen *= B.ncp[a];
+        }
+        if (B.knot_off < 0 || B.knot_off + klen > nknots) return FA_ERR_INVALID_ARG;
+        if (B.ctrl_off < 0 || B.ctrl_off % 4 != 0 || B.ctrl_off + clen > nctrl)
+            return FA_ERR_INVALID_ARG;
+        if (worst != FA_OK) continue;
+        const float *t = knots + B.knot_off;
+        for (int a = 0; a < 3; ++a) {
+            const int n = B.ncp[a];
+            for (int j = 0; j <= p; ++j)
+                if (t[j] != 0.0f || t[n + j] != 1.0f) return FA_ERR_INVALID_ARG;
+            for (int j = 1; j < n + p + 1; ++j)
+                if (!(t[j] >= t[j - 1])) return FA_ERR_INVALID_ARG;
+            bool uni = true;
+            for (int j = 0; j <= n - p && uni; ++j)
+                uni = t[p + j] == (float)j / (float)(n - p);
+            if (uni) flags[b] |= (1u << a);
+            t += n + p + 1;
+        }
+    }
+    if (worst != FA_OK) return worst;
+    for (int32_t b = 0; b < nblocks; ++b) blocks[b].flags = flags[b];
+    return FA_OK;
+}
+
+fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t res[3],
+                         const fa_tune *tune, fa_work *work, int32_t *wg_off,
+                         int64_t capacity, int64_t *nwork, int32_t *ngroups) {
+    if (!blocks || nblocks <= 0 || !res_ok(res) || !work || !wg_off || !nwork || !ngroups)
+        return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    const Tune t = resolve(tune);
+    if (!waves_ok(t.waves) || t.rows > 64) return FA_ERR_INVALID_ARG;
+    const int nrowt = (res[1] + t.rows - 1) / t.rows;
+    const int ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
+    const int64_t n = (int64_t)nblocks * nrowt * ncolt;
+    if (capacity < n) return FA_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const int p = blocks[b].degree[0];
+        if (p < 1 || p > FA_MAX_DEGREE) return FA_ERR_INVALID_ARG;
+        for (int a = 0; a < 3; ++a)
+            if (blocks[b].ncp[a] < p + 1 || blocks[b].ncp[a] > FA_MAX_NCP)
+                return FA_ERR_INVALID_ARG;
+    }
+    // items and their cost: stores + banded x stage per voxel, the on-the-fly
+    // (z, y) contraction per column and x plane, the per-item set-up
+    std::vector<fa_work> items(n);
+    std::vector<double> cost(n);
+    int64_t q = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const fa_block &B = blocks[b];
+        const int p = B.degree[0], nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
+        const double per_vox = 4.0 + 4.0 * (p + 1);
+        const double per_col_plane = 2.0 * (p + 1) * (p + 1) + 3.0 * (p + 1);
+        for (int rt = 0; rt < nrowt; ++rt) {
+            const int row0 = rt * t.rows;
+            const int nrows = std::min(t.rows, res[1] - row0);
+            const double jn = std::min<double>(ny, (double)(nrows - 1) * (ny - p) / (res[1] - 1) + p + 2);
+            for (int ct = 0; ct < ncolt; ++ct) {
+                const int col0 = ct * kWaveLanes;
+                const int ncols = std::min(kWaveLanes, res[2] - col0);
+                items[q] = fa_work{b, (int16_t)row0, (int16_t)nrows, (int16_t)col0, 0};
+                cost[q] = (double)res[0] * nrows * ncols * per_vox +
+                          (double)nrows * ncols * nx * per_col_plane + 40.0 * res[0] +
+                          2.0 * nx * jn * nz;
+                ++q;
+            }
+        }
+    }
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, t.grid > 0 ? t.grid : kDefaultGrid));
+    // longest processing time first onto the least loaded workgroup
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    using Slot = std::pair<double, int>;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int g = 0; g < grid; ++g) heap.push({0.0, g});
+    std::vector<int> owner(n);
+    std::vector<int32_t> count(grid, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        Slot s = heap.top();
+        heap.pop();
+        owner[order[k]] = s.second;
+        count[s.second]++;
+        heap.push({s.first + cost[order[k]], s.second});
+    }
+    wg_off[0] = 0;
+    for (int g = 0; g < grid; ++g) wg_off[g + 1] = wg_off[g] + count[g];
+    std::vector<int32_t> fill(wg_off, wg_off + grid);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t it = order[k];
+        work[fill[owner[it]]++] = items[it];
+    }
+    *nwork = n;
+    *ngroups = grid;
+    return FA_OK;
+}
+
+fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
+                           const void *ctrl, fa_dtype dtype, const int32_t res[3],
+                           uint32_t mask, const fa_tune *tune, const fa_work *work,
+                           const int32_t *wg_off, int32_t ngroups, float *out,
+                           void *stream) {
+    if (!blocks || !knots || !ctrl || !out || nblocks <= 0 || !res_ok(res) ||
+        (mask & 15u) == 0 || (mask & ~15u) != 0)
+        return FA_ERR_INVALID_ARG;
+    if (dtype != FA_F32 && dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
+    if ((work == nullptr) != (wg_off == nullptr)) return FA_ERR_INVALID_ARG;
+    if (work && ngroups <= 0) return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    const Tune t = resolve(tune);
+    if (!waves_ok(t.waves) || t.rows > 64) return FA_ERR_INVALID_ARG;
+    DecodeLaunch a{};
+    a.blocks = blocks;
+    a.knots = knots;
+    a.ctrl = ctrl;
+    a.dtype = dtype;
+    a.rx = res[0];
+    a.ry = res[1];
+    a.rz = res[2];
+    a.mask = mask;
+    a.nch = popcount4(mask);
+    a.work = work;
+    a.wg_off = wg_off;
+    a.rows = t.rows;
+    a.nrowt = (res[1] + t.rows - 1) / t.rows;
+    a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
+    a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
+    a.out = out;
+    int grid = work ? ngroups
+                    : (int)std::min<int64_t>(a.nitems, t.grid > 0 ? t.grid : kDefaultGrid);
+    hipError_t e;
+    if (t.kernel == 1) e = launch_decode_mfma(a, t.waves, grid, (hipStream_t)stream);
+    else if (t.kernel == 0) e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
+    else return FA_ERR_INVALID_ARG;
+    if (e == hipErrorNotSupported) return FA_ERR_UNSUPPORTED;
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+fa_status fa_decode_blocks_plain(const fa_block *blocks, int32_t nblocks, const float *knots,
+                                 const float *ctrl, const int32_t res[3], uint32_t mask,
+                                 float *out, void *stream) {
+    if (!blocks || !knots || !ctrl || !out || nblocks <= 0 || !res_ok(res) ||
+        (mask & 15u) == 0 || (mask & ~15u) != 0)
+        return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    hipError_t e = launch_decode_plain(blocks, nblocks, knots, ctrl, res[0], res[1], res[2],
+                                       mask, out, (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
+                          const int32_t *block_of_cell, const int32_t nb[3],
+                          const float origin[3], const float extent[3], const float *knots,
+                          const void *ctrl, fa_dtype dtype, const float *xyz, int64_t n,
+                          uint32_t mask, float *out, void *stream) {
+    if (!blocks || nblocks <= 0 || !block_of_cell || !nb || !origin || !extent || !knots ||
+        !ctrl || n < 0 || (n > 0 && (!xyz || !out)) || (mask & 15u) == 0 ||
+        (mask & ~15u) != 0)
+        return FA_ERR_INVALID_ARG;
+    if (dtype != FA_F32 && dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
+    QueryLaunch a{};
+    for (int k = 0; k < 3; ++k) {
+        if (nb[k] <= 0 || !(extent[k] > 0.0f) || !std::isfinite(origin[k]) ||
+            !std::isfinite(extent[k]))
+            return FA_ERR_INVALID_ARG;
+        a.nb[k] = nb[k];
+        a.origin[k] = origin[k];
+        a.rscale[k] = (float)nb[k] / extent[k];
+    }
+    if ((int64_t)nb[0] * nb[1] * nb[2] > (int64_t)1 << 30) return FA_ERR_UNSUPPORTED;
+    a.blocks = blocks;
+    a.nblocks = nblocks;
+    a.block_of_cell = block_of_cell;
+    a.knots = knots;
+    a.ctrl = ctrl;
+    a.dtype = dtype;
+    a.xyz = xyz;
+    a.n = n;
+    a.mask = mask;
+    a.out = out;
+    hipError_t e = launch_query(a, (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
+                             const int32_t res[3], uint32_t mask, const float *grad_out,
+                             float *grad_ctrl, int32_t rows_per_item, void *stream) {
+    if (!blocks || nblocks <= 0 || !knots || !res_ok(res) || !grad_out || !grad_ctrl ||
+        (mask & 15u) == 0 || (mask & ~15u) != 0 || rows_per_item < 0)
+        return FA_ERR_INVALID_ARG;
+    if (!res_supported(res) || res[1] > 64 || res[2] > 64) return FA_ERR_UNSUPPORTED;
+    hipError_t e = launch_adjoint(blocks, nblocks, knots, res[0], res[1], res[2], mask,
+                                  grad_out, grad_ctrl, rows_per_item ? rows_per_item : 2,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctrl_f32,
+                             fa_dtype dtype, void *ctrl_lp, void *stream) {
+    if (!blocks || nblocks <= 0 || !ctrl_f32 || !ctrl_lp) return FA_ERR_INVALID_ARG;
+    if (dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
+    hipError_t e = launch_quantize(blocks, nblocks, ctrl_f32, dtype, ctrl_lp,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+}  // extern "C"

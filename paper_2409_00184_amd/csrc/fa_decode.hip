@@ -1,0 +1,339 @@
+// Grid decode of batched micro-models on gfx950 (FP32 VALU forms).
+//
+// decode_sep: the batched, persistent, separable form (rows a0-a6).
+//   The tensor-product sum over the (p+1)^3 window factorises per axis, so
+//   one column (v, w) of a work item is decoded as
+//     T_B[j] = sum_k Bz[w][k] P[i][j][k],   T_D[j] = sum_k Dz[w][k] P[i][j][k]
+//     U_BB[i] = sum_j By[v][j] T_B[j],  U_DB[i] = sum_j Dy[v][j] T_B[j],
+//     U_BD[i] = sum_j By[v][j] T_D[j]
+//     value = sum_i Bx[u][i] U_BB[i], d/du = sum_i Dx[u][i] U_BB[i],
+//     d/dv  = sum_i Bx[u][i] U_DB[i], d/dw = sum_i Bx[u][i] U_BD[i]
+//   with every sum banded to the p+1 non-zero basis functions.  A lane owns
+//   one (v, w) column (lanes along z, so every store is a contiguous 256 B
+//   row) and walks u = 0..Rx-1 keeping the p+1 newest U values in
+//   registers; U[i] is built on the fly from a lattice slab staged once per
+//   work item in LDS.  The x-axis basis (span + p+1 values + p+1
+//   derivatives per u) is tabulated in LDS once per item and read as
+//   broadcasts.  Work items are (block, y-row range, 64-wide z chunk); a
+//   workgroup runs the items a host plan assigned to it, or a grid-stride
+//   share of the default order.
+//
+// decode_plain: the baseline -- one thread per voxel, one launch per block,
+//   each thread doing its own span searches, basis evaluation and (p+1)^3
+//   window sum straight from global memory.
+#include "fa_device.hpp"
+#include "fa_internal.hpp"
+
+namespace fa {
+namespace {
+
+struct SepSmem {
+    float4 xB[kMaxRes];
+    float4 xD[kMaxRes];
+    int xS[kMaxRes];
+    float kn[kMaxKnotsPerBlock + 4];
+    float slab[kSlabFloats];
+};
+
+template <int P>
+__device__ __forceinline__ float4 pack4(const float (&v)[P + 1]) {
+    float4 r;
+    r.x = v[0];
+    r.y = P >= 1 ? v[P >= 1 ? 1 : 0] : 0.0f;
+    r.z = P >= 2 ? v[P >= 2 ? 2 : 0] : 0.0f;
+    r.w = P >= 3 ? v[P >= 3 ? 3 : 0] : 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ float comp(const float4 &v, int r) {
+    return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
+}
+
+template <int P>
+__device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0,
+                         SepSmem &sm) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
+    const fa_block &B = a.blocks[b];
+    const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
+    const int64_t koff = B.knot_off, coff = B.ctrl_off;
+    const float scale = B.scale;
+    const int nkn = nx + ny + nz + 3 * (P + 1);
+
+    __syncthreads();  // the previous item is done with the shared buffers
+    for (int e = tid; e < nkn; e += nthr) sm.kn[e] = a.knots[koff + e];
+    __syncthreads();
+    const float *tx = sm.kn;
+    const float *ty = tx + nx + P + 1;
+    const float *tz = ty + ny + P + 1;
+
+    // x table: span and basis of every grid position along x
+    for (int u = tid; u < a.rx; u += nthr) {
+        const float uu = grid_pos(u, a.rx);
+        const int s = span_search(nx, P, tx, uu);
+        float N[P + 1], D[P + 1];
+        basis_ders<P>(tx, s, uu, N, D);
+        sm.xB[u] = pack4<P>(N);
+        sm.xD[u] = pack4<P>(D);
+        sm.xS[u] = s;
+    }
+
+    // lattice rows j in [jlo, jhi] cover the y windows of every row of the item
+    const int jlo = span_search(ny, P, ty, grid_pos(row0, a.ry)) - P;
+    const int jhi = span_search(ny, P, ty, grid_pos(row0 + nrows - 1, a.ry));
+    const int plane = (jhi - jlo + 1) * nz;  // slab floats per x plane
+    const int ic = min(nx, kSlabFloats / plane);
+    const bool single = (ic == nx);
+
+    // z basis of this lane's column
+    const bool wok = (col0 + lane) < a.rz;
+    const int w = wok ? col0 + lane : a.rz - 1;
+    const float zw = grid_pos(w, a.rz);
+    const int sz = span_search(nz, P, tz, zw);
+    float zB[P + 1], zD[P + 1];
+    basis_ders<P>(tz, sz, zw, zB, zD);
+    const int kz0 = sz - P;
+
+    auto stage = [&](int c0, int c1) {
+        const int cnt = (c1 - c0) * plane;
+        for (int e = tid; e < cnt; e += nthr) {
+            const int ii = e / plane;
+            const int r = e - ii * plane;
+            const int64_t gi = coff + (int64_t)((c0 + ii) * ny + jlo) * nz + r;
+            sm.slab[e] = load_ctrl(a.ctrl, a.dtype, gi, scale);
+        }
+    };
+
+    __syncthreads();  // x table visible
+    if (single) {
+        stage(0, nx);
+        __syncthreads();
+    }
+
+    const int64_t vox = (int64_t)a.rx * a.ry * a.rz;
+    const int64_t plane_out = (int64_t)a.ry * a.rz;
+    int64_t choff[4];
+    {
+        int c = 0;
+        for (int ch = 0; ch < 4; ++ch) {
+            choff[ch] = (int64_t)c * vox;
+            c += (a.mask >> ch) & 1u;
+        }
+    }
+
+    for (int rb = 0; rb < nrows; rb += nwaves) {
+        const int rr = rb + wave;
+        const bool rok = rr < nrows;
+        const int v = row0 + (rok ? rr : nrows - 1);
+        const float yv = grid_pos(v, a.ry);
+        const int sy = span_search(ny, P, ty, yv);
+        float yB[P + 1], yD[P + 1];
+        basis_ders<P>(ty, sy, yv, yB, yD);
+        const int jrow = sy - P - jlo;
+
+        int clo = 0, chi = ic;
+        if (!single) {
+            __syncthreads();
+            stage(0, ic);
+            __syncthreads();
+        }
+
+        float wBB[P + 1], wDB[P + 1], wBD[P + 1];
+#pragma unroll
+        for (int r = 0; r <= P; ++r) wBB[r] = wDB[r] = wBD[r] = 0.0f;
+        int top = -1;
+        float *ob = a.out + (int64_t)b * a.nch * vox + (int64_t)v * a.rz + w;
+        const bool live = rok && wok;
+
+        for (int u = 0; u < a.rx; ++u) {
+            const int s = sm.xS[u];
+            while (top < s) {  // uniform over the workgroup
+                ++top;
+                if (top >= chi) {
+                    __syncthreads();
+                    clo = chi;
+                    chi = min(clo + ic, nx);
+                    stage(clo, chi);
+                    __syncthreads();
+                }
+                const float *sl = sm.slab + (top - clo) * plane + jrow * nz + kz0;
+                float tB[P + 1], tD[P + 1];
+#pragma unroll
+                for (int jj = 0; jj <= P; ++jj) {
+                    float x = 0.0f, y = 0.0f;
+#pragma unroll
+                    for (int kk = 0; kk <= P; ++kk) {
+                        const float c = sl[jj * nz + kk];
+                        x = fmaf(zB[kk], c, x);
+                        y = fmaf(zD[kk], c, y);
+                    }
+                    tB[jj] = x;
+                    tD[jj] = y;
+                }
+                float uBB = 0.0f, uDB = 0.0f, uBD = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj <= P; ++jj) {
+                    uBB = fmaf(yB[jj], tB[jj], uBB);
+                    uDB = fmaf(yD[jj], tB[jj], uDB);
+                    uBD = fmaf(yB[jj], tD[jj], uBD);
+                }
+#pragma unroll
+                for (int r = 0; r < P; ++r) {
+                    wBB[r] = wBB[r + 1];
+                    wDB[r] = wDB[r + 1];
+                    wBD[r] = wBD[r + 1];
+                }
+                wBB[P] = uBB;
+                wDB[P] = uDB;
+                wBD[P] = uBD;
+            }
+            const float4 bx = sm.xB[u];
+            const float4 dx = sm.xD[u];
+            float val = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) {
+                const float cb = comp(bx, r), cd = comp(dx, r);
+                val = fmaf(cb, wBB[r], val);
+                gx = fmaf(cd, wBB[r], gx);
+                gy = fmaf(cb, wDB[r], gy);
+                gz = fmaf(cb, wBD[r], gz);
+            }
+            if (live) {
+                float *o = ob + (int64_t)u * plane_out;
+                if (a.mask & 1u) __builtin_nontemporal_store(val, o + choff[0]);
+                if (a.mask & 2u) __builtin_nontemporal_store(gx, o + choff[1]);
+                if (a.mask & 4u) __builtin_nontemporal_store(gy, o + choff[2]);
+                if (a.mask & 8u) __builtin_nontemporal_store(gz, o + choff[3]);
+            }
+        }
+    }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) {
+    __shared__ SepSmem sm;
+    int64_t beg, end, step;
+    if (a.work) {
+        beg = a.wg_off[blockIdx.x];
+        end = a.wg_off[blockIdx.x + 1];
+        step = 1;
+    } else {
+        beg = blockIdx.x;
+        end = a.nitems;
+        step = gridDim.x;
+    }
+    const int64_t per = (int64_t)a.nrowt * a.ncolt;
+    for (int64_t it = beg; it < end; it += step) {
+        int b, row0, nrows, col0;
+        if (a.work) {
+            const fa_work wk = a.work[it];
+            b = wk.block;
+            row0 = wk.row0;
+            nrows = wk.nrows;
+            col0 = wk.col0;
+        } else {
+            b = (int)(it / per);
+            const int r = (int)(it - (int64_t)b * per);
+            row0 = (r / a.ncolt) * a.rows;
+            nrows = min(a.rows, a.ry - row0);
+            col0 = (r % a.ncolt) * kWave;
+        }
+        const int p = a.blocks[b].degree[0];
+        if (p == 3) sep_item<3>(a, b, row0, nrows, col0, sm);
+        else if (p == 2) sep_item<2>(a, b, row0, nrows, col0, sm);
+        else sep_item<1>(a, b, row0, nrows, col0, sm);
+    }
+}
+
+// ------------------------------------------------------------------ plain
+
+template <int P>
+__device__ __forceinline__ void plain_voxel(const fa_block &B, const float *knots,
+                                            const float *ctrl, int u, int v, int w, int rx,
+                                            int ry, int rz, float (&res)[4]) {
+    const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
+    const float *tx = knots + B.knot_off;
+    const float *ty = tx + nx + P + 1;
+    const float *tz = ty + ny + P + 1;
+    const float pu = grid_pos(u, rx), pv = grid_pos(v, ry), pw = grid_pos(w, rz);
+    const int su = span_search(nx, P, tx, pu);
+    const int sv = span_search(ny, P, ty, pv);
+    const int sw = span_search(nz, P, tz, pw);
+    float xB[P + 1], xD[P + 1], yB[P + 1], yD[P + 1], zB[P + 1], zD[P + 1];
+    basis_ders<P>(tx, su, pu, xB, xD);
+    basis_ders<P>(ty, sv, pv, yB, yD);
+    basis_ders<P>(tz, sw, pw, zB, zD);
+    float f = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    const float *base = ctrl + B.ctrl_off;
+    for (int i = 0; i <= P; ++i) {
+        for (int j = 0; j <= P; ++j) {
+            for (int k = 0; k <= P; ++k) {
+                const float c = base[((int64_t)(su - P + i) * ny + (sv - P + j)) * nz + (sw - P + k)];
+                f += xB[i] * yB[j] * zB[k] * c;
+                fx += xD[i] * yB[j] * zB[k] * c;
+                fy += xB[i] * yD[j] * zB[k] * c;
+                fz += xB[i] * yB[j] * zD[k] * c;
+            }
+        }
+    }
+    res[0] = f;
+    res[1] = fx;
+    res[2] = fy;
+    res[3] = fz;
+}
+
+__global__ __launch_bounds__(256) void decode_plain_kernel(const fa_block *blocks, int b,
+                                                           const float *knots,
+                                                           const float *ctrl, int rx, int ry,
+                                                           int rz, uint32_t mask, int nch,
+                                                           float *out) {
+    const int64_t vox = (int64_t)rx * ry * rz;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= vox) return;
+    const int w = (int)(idx % rz);
+    const int v = (int)((idx / rz) % ry);
+    const int u = (int)(idx / ((int64_t)ry * rz));
+    const fa_block &B = blocks[b];
+    float res[4];
+    const int p = B.degree[0];
+    if (p == 3) plain_voxel<3>(B, knots, ctrl, u, v, w, rx, ry, rz, res);
+    else if (p == 2) plain_voxel<2>(B, knots, ctrl, u, v, w, rx, ry, rz, res);
+    else plain_voxel<1>(B, knots, ctrl, u, v, w, rx, ry, rz, res);
+    float *o = out + (int64_t)b * nch * vox + idx;
+    int c = 0;
+    for (int ch = 0; ch < 4; ++ch) {
+        if ((mask >> ch) & 1u) {
+            o[(int64_t)c * vox] = res[ch];
+            ++c;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
+    switch (waves) {
+    case 2: hipLaunchKernelGGL(decode_sep_kernel<2>, dim3(grid), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(decode_sep_kernel<4>, dim3(grid), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(decode_sep_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL(decode_sep_kernel<1>, dim3(grid), dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,
+                               const float *ctrl, int rx, int ry, int rz, uint32_t mask,
+                               float *out, hipStream_t s) {
+    const int64_t vox = (int64_t)rx * ry * rz;
+    const int nch = __builtin_popcount(mask & 15u);
+    const int grid = (int)((vox + 255) / 256);
+    for (int b = 0; b < nblocks; ++b) {
+        hipLaunchKernelGGL(decode_plain_kernel, dim3(grid), dim3(256), 0, s, blocks, b, knots,
+                           ctrl, rx, ry, rz, mask, nch, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace fa

@@ -1,0 +1,63 @@
+// Launchers shared between the C ABI (fa_api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fa.h"
+
+namespace fa {
+
+// Fixed LDS budget of the separable decode (floats).
+constexpr int kWaveLanes = 64;
+constexpr int kSlabFloats = 8192;     // lattice slab
+constexpr int kMaxRes = FA_MAX_RES;   // x-table rows
+
+struct DecodeLaunch {
+    const fa_block *blocks;
+    const float *knots;
+    const void *ctrl;
+    int dtype;
+    int rx, ry, rz;
+    uint32_t mask;
+    int nch;
+    const fa_work *work;     // may be null: default order
+    const int32_t *wg_off;
+    int rows;                // rows per item in default order
+    int nrowt, ncolt;        // tiles per block (default order)
+    int64_t nitems;          // items in default order
+    float *out;
+};
+
+hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s);
+hipError_t launch_decode_mfma(const DecodeLaunch &a, int waves, int grid, hipStream_t s);
+hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,
+                               const float *ctrl, int rx, int ry, int rz, uint32_t mask,
+                               float *out, hipStream_t s);
+
+struct QueryLaunch {
+    const fa_block *blocks;
+    int nblocks;
+    const int32_t *block_of_cell;
+    int nb[3];
+    float origin[3];
+    float rscale[3];  // (float)nb / extent
+    const float *knots;
+    const void *ctrl;
+    int dtype;
+    const float *xyz;
+    int64_t n;
+    uint32_t mask;
+    float *out;
+};
+
+hipError_t launch_query(const QueryLaunch &a, hipStream_t s);
+
+hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
+                          int ry, int rz, uint32_t mask, const float *g, float *G, int it,
+                          hipStream_t s);
+
+hipError_t launch_quantize(fa_block *blocks, int nblocks, const float *ctrl, int dtype,
+                           void *out, hipStream_t s);
+
+}  // namespace fa

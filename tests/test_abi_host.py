@@ -1,0 +1,175 @@
+"""The C-ABI library loads, exports every symbol include/fa.h declares, and
+its host-only calls (validation, batch plan) behave as documented (CPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fa_inputs as fi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fa.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fa_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def fa():
+    import paper_2409_00184_amd as fa
+    return fa
+
+
+def test_exports_every_declared_symbol(fa):
+    names = declared_functions()
+    assert {"fa_decode_blocks", "fa_query_points", "fa_decode_backward"} <= set(names)
+    raw = ctypes.CDLL(fa.library_path())
+    for n in names:
+        assert hasattr(raw, n), n
+    assert fa.lib.fa_version() >= 10000
+
+
+def test_struct_layouts(fa):
+    assert fa.BLOCK_DTYPE.itemsize == 64
+    assert fa.BLOCK_DTYPE.fields["knot_off"][1] == 24
+    assert fa.BLOCK_DTYPE.fields["ctrl_off"][1] == 32
+    assert fa.BLOCK_DTYPE.fields["scale"][1] == 40
+    assert fa.WORK_DTYPE.itemsize == 12
+
+
+def _desc(fa, b):
+    return fa.host_descriptors(b.ncp, b.deg, b.knot_off, b.ctrl_off)
+
+
+def test_validate_sets_uniform_flags(fa):
+    b = fi.config_c2(nblocks=8)
+    d = fa.fa_validate_blocks(_desc(fa, b), b.knots, b.ctrl.size)
+    assert np.all(d["flags"] == 7)
+    # a non-uniform interior knot clears that axis' flag only
+    k = b.knots.copy()
+    n, p = b.ncp[0], b.deg[0]
+    k[int(b.knot_off[0]) + p[0] + 1] *= 0.5
+    d = fa.fa_validate_blocks(_desc(fa, b), k, b.ctrl.size)
+    assert d["flags"][0] == 6 and np.all(d["flags"][1:] == 7)
+
+
+@pytest.mark.parametrize("case", ["ncp_small", "deg_mixed", "knot_oob", "ctrl_oob",
+                                  "unclamped", "decreasing", "nan_knot", "misaligned"])
+def test_validate_rejects(fa, case):
+    b = fi.config_c2(nblocks=4)
+    d = _desc(fa, b)
+    k = b.knots.copy()
+    nctrl = b.ctrl.size
+    if case == "ncp_small":
+        d["ncp"][1, 2] = d["degree"][1, 2]
+    elif case == "deg_mixed":
+        d["degree"][2, 1] = 1 if d["degree"][2, 0] != 1 else 2
+    elif case == "knot_oob":
+        d["knot_off"][3] = len(k)
+    elif case == "ctrl_oob":
+        nctrl = int(b.ctrl_off[3]) + 10
+    elif case == "unclamped":
+        k[int(b.knot_off[2])] = 0.01
+    elif case == "decreasing":
+        o = int(b.knot_off[1]) + int(b.deg[1, 0]) + 2
+        k[o] = k[o - 1] - 0.01
+    elif case == "nan_knot":
+        k[int(b.knot_off[0]) + int(b.deg[0, 0]) + 1] = np.nan
+    elif case == "misaligned":
+        d["ctrl_off"][1] += 1
+    before = d.copy()
+    with pytest.raises(fa.FAError) as e:
+        fa.fa_validate_blocks(d, k, nctrl)
+    assert e.value.status == 1
+    assert np.array_equal(d, before), "nothing is written on error"
+
+
+def test_validate_unsupported(fa):
+    b = fi.pack([(70, 8, 8)], [(3, 3, 3)],
+                [[fi.clamped_uniform_knots(70, 3), fi.clamped_uniform_knots(8, 3),
+                  fi.clamped_uniform_knots(8, 3)]], [np.zeros((70, 8, 8))])
+    with pytest.raises(fa.FAError) as e:
+        fa.fa_validate_blocks(_desc(fa, b), b.knots, b.ctrl.size)
+    assert e.value.status == 2
+
+
+def _plan(fa, d, res, rows, waves, grid):
+    cap = len(d) * res[1] * ((res[2] + 63) // 64)
+    work = np.zeros(cap, fa.WORK_DTYPE)
+    off = np.zeros(cap + 1, np.int32)
+    nw, ng = ctypes.c_int64(), ctypes.c_int32()
+    t = fa.FATune(rows, waves, grid, 0)
+    st = fa.lib.fa_plan_decode(d.ctypes.data, len(d), fa._i32x3(res), ctypes.byref(t),
+                               work.ctypes.data, off.ctypes.data, cap, ctypes.byref(nw),
+                               ctypes.byref(ng))
+    return st, work[:nw.value], off[:ng.value + 1]
+
+
+@pytest.mark.parametrize("res,rows,grid", [((64, 64, 64), 8, 768), ((17, 23, 70), 4, 7),
+                                           ((5, 3, 2), 8, 1000)])
+def test_plan_covers_every_item_once(fa, res, rows, grid):
+    b = fi.config_c2(nblocks=37)
+    d = fa.fa_validate_blocks(_desc(fa, b), b.knots, b.ctrl.size)
+    st, work, off = _plan(fa, d, res, rows, 4, grid)
+    assert st == 0
+    nrowt = -(-res[1] // rows)
+    ncolt = -(-res[2] // 64)
+    assert len(work) == 37 * nrowt * ncolt
+    assert off[0] == 0 and off[-1] == len(work) and np.all(np.diff(off) >= 0)
+    assert len(off) - 1 == min(grid, len(work))
+    # every voxel row of every block appears exactly once
+    cover = np.zeros((37, res[1], ncolt), np.int32)
+    for w in work:
+        assert 0 < w["nrows"] <= rows and w["row0"] % rows == 0 and w["col0"] % 64 == 0
+        cover[w["block"], w["row0"]:w["row0"] + w["nrows"], w["col0"] // 64] += 1
+    assert np.all(cover == 1)
+
+
+def test_plan_balances_uneven_blocks(fa):
+    """LPT on the cost model: the heaviest workgroup carries at most the
+    mean load plus one item (the classic LPT guarantee is 4/3 of optimal)."""
+    b = fi.config_c2(nblocks=512)
+    d = fa.fa_validate_blocks(_desc(fa, b), b.knots, b.ctrl.size)
+    st, work, off = _plan(fa, d, (64, 64, 64), 8, 4, 768)
+    assert st == 0
+    counts = np.diff(off)
+    assert counts.max() - counts.min() <= 2
+
+
+def test_plan_rejects_small_capacity(fa):
+    b = fi.config_c2(nblocks=4)
+    d = fa.fa_validate_blocks(_desc(fa, b), b.knots, b.ctrl.size)
+    work = np.zeros(3, fa.WORK_DTYPE)
+    off = np.zeros(4, np.int32)
+    nw, ng = ctypes.c_int64(), ctypes.c_int32()
+    st = fa.lib.fa_plan_decode(d.ctypes.data, 4, fa._i32x3((64, 64, 64)), None,
+                               work.ctypes.data, off.ctypes.data, 3, ctypes.byref(nw),
+                               ctypes.byref(ng))
+    assert st == 1
+
+
+def test_hot_calls_reject_bad_arguments_without_launch(fa):
+    """Argument errors return before any launch (no GPU is touched here)."""
+    L = fa.lib
+    vp = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
+    r = fa._i32x3((64, 64, 64))
+    assert L.fa_decode_blocks(None, 1, vp, vp, 0, r, 15, None, None, None, 0, vp, None) == 1
+    assert L.fa_decode_blocks(vp, 0, vp, vp, 0, r, 15, None, None, None, 0, vp, None) == 1
+    assert L.fa_decode_blocks(vp, 1, vp, vp, 0, r, 0, None, None, None, 0, vp, None) == 1
+    assert L.fa_decode_blocks(vp, 1, vp, vp, 7, r, 15, None, None, None, 0, vp, None) == 1
+    assert L.fa_decode_blocks(vp, 1, vp, vp, 0, fa._i32x3((1, 4, 4)), 15, None, None, None, 0,
+                              vp, None) == 1
+    assert L.fa_decode_blocks(vp, 1, vp, vp, 0, fa._i32x3((300, 4, 4)), 15, None, None, None,
+                              0, vp, None) == 2
+    assert L.fa_decode_blocks(vp, 1, vp, vp, 0, r, 15, None, vp, None, 0, vp, None) == 1
+    assert L.fa_query_points(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
+                             fa._f32x3((1, 0, 1)), vp, vp, 0, vp, 5, 15, vp, None) == 1
+    assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, 0, None) == 2
+    assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
+    assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
+    assert L.fa_decode_blocks_plain(vp, 1, vp, None, r, 15, vp, None) == 1

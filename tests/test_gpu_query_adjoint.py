@@ -1,0 +1,143 @@
+"""Point query and the decode adjoint on the GPU against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import fa_inputs as fi
+import oracle
+from gpu_util import check_elementwise_bound, check_normwise, mixed_batch, models, oracle_blocks, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fa():
+    import paper_2409_00184_amd as fa
+    assert torch.cuda.is_available()
+    return fa
+
+
+def _query_case(fa, b, nb, origin, extent, boc, xyz, what, mask=15):
+    m = models(b)
+    q = fa.query(m, torch.as_tensor(xyz).cuda().contiguous(), nb, origin, extent,
+                 torch.as_tensor(boc, dtype=torch.int32).cuda(), mask).cpu().numpy()
+    r, S = oracle.query_points(oracle_blocks(b), xyz, nb, origin, extent, boc, with_abs=True)
+    for c in range(4):
+        if not (mask >> c) & 1:
+            r[:, c] = 0.0
+            S[:, c] = 0.0
+    check_elementwise_bound(q, r, S, 64.0, what)
+    return q, r
+
+
+def test_query_mixed_domain(fa):
+    """2x3x2 cells, permuted cell map with an empty cell, non-unit
+    origin/extent, points inside, outside (clamped), on faces and knots."""
+    say("query mixed")
+    nb = (2, 3, 2)
+    b = mixed_batch(31, 12)
+    g = fi.rng(32)
+    boc = g.permutation(12).astype(np.int32)
+    boc[5] = -1
+    origin = np.array([-0.5, 0.25, 1.0], np.float32)
+    extent = np.array([2.0, 3.0, 0.5], np.float32)
+    u = g.uniform(-0.1, 1.1, (20000, 3))
+    faces = (g.integers(0, 7, (2000, 3)) / 6.0)  # multiples of 1/6: cell faces for nb 2,3
+    u = np.concatenate([u, faces, [[0, 0, 0], [1, 1, 1]]])
+    xyz = (origin + u * extent).astype(np.float32)
+    for mask in (15, 1, 0b1010):
+        _query_case(fa, b, nb, origin, extent, boc, xyz, f"query mixed mask {mask}", mask)
+
+
+def test_query_c3_blocks_rays(fa):
+    """Config C3 micro-models (16^3 blocks, NCP* in 8..32, cubic) queried by
+    seeded camera rays (reduced image: 160 x 90 rays, 512 samples each)."""
+    say("query C3 reduced rays")
+    b = fi.config_c3_blocks()
+    xyz = fi.ray_samples_np(3, 160, 90, 512)
+    q, r = _query_case(fa, b, (16, 16, 16), (0, 0, 0), (1, 1, 1), fi.identity_cells(16 ** 3),
+                       xyz, "C3 rays")
+    scale = np.abs(r).max(0)
+    assert np.all(np.abs(q - r).max(0) <= 1e-5 * scale)
+
+
+def test_query_c3_full_sampled(fa):
+    """C3 at full size: 1920x1080 rays x 512 samples generated on the GPU
+    (1.06e9 samples); 300k sampled outputs checked against the oracle."""
+    say("query C3 full")
+    b = fi.config_c3_blocks()
+    m = models(b)
+    o, d, t0, t1, j = fi.camera_rays(3, 1920, 1080)
+    nray, ns = o.shape[0], 512
+    dev = "cuda"
+    O = torch.as_tensor(o, dtype=torch.float64, device=dev)
+    D = torch.as_tensor(d, dtype=torch.float64, device=dev)
+    T0 = torch.as_tensor(t0, dtype=torch.float64, device=dev)
+    T1 = torch.as_tensor(t1, dtype=torch.float64, device=dev)
+    J = torch.as_tensor(j, dtype=torch.float64, device=dev)
+    xyz = torch.empty((nray, ns, 3), dtype=torch.float32, device=dev)
+    s = torch.arange(ns, dtype=torch.float64, device=dev)
+    for r0 in range(0, nray, 1 << 18):
+        r1 = min(nray, r0 + (1 << 18))
+        t = T0[r0:r1, None] + (s[None] + J[r0:r1, None]) / ns * (T1 - T0)[r0:r1, None]
+        xyz[r0:r1] = (O[r0:r1, None] + D[r0:r1, None] * t[..., None]).float()
+    xyz = xyz.reshape(-1, 3)
+    boc = torch.as_tensor(fi.identity_cells(4096), device=dev)
+    out = fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc)
+    torch.cuda.synchronize()
+    g = fi.rng(33)
+    idx = torch.as_tensor(g.integers(0, xyz.shape[0], 300000), device=dev)
+    xs = xyz[idx].cpu().numpy()
+    got = out[idx].cpu().numpy()
+    del out, xyz
+    r, S = oracle.query_points(oracle_blocks(b), xs, (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                               fi.identity_cells(4096), with_abs=True)
+    check_elementwise_bound(got, r, S, 64.0, "C3 full sampled")
+
+
+@pytest.mark.parametrize("mask", [1, 15, 0b0110, 8])
+@pytest.mark.parametrize("res", [(17, 23, 29), (64, 64, 64), (40, 3, 64)])
+def test_adjoint_vs_oracle(fa, mask, res):
+    say("adjoint", mask, res)
+    b = mixed_batch(41, 10, ncp_hi=24)
+    m = models(b)
+    nchan = bin(mask).count("1")
+    g = torch.randn((b.nblocks, nchan) + res, generator=torch.Generator().manual_seed(42))
+    G = fa.decode_backward(m, res, g.cuda().contiguous(), mask).cpu().numpy()
+    Gr = oracle.decode_adjoint(oracle_blocks(b), res, g.numpy().astype(np.float64), mask)
+    for bb in range(b.nblocks):
+        o = int(b.ctrl_off[bb])
+        k = int(np.prod(b.ncp[bb]))
+        err = np.abs(G[o:o + k] - Gr[o:o + k]).max()
+        assert err <= 1e-5 * np.abs(Gr[o:o + k]).max(), (bb, err)
+
+
+def test_adjoint_dot_product(fa):
+    """<B P, g> = <P, B^T g> with the GPU forward and the GPU adjoint."""
+    say("adjoint dot")
+    b = mixed_batch(43, 16, ncp_hi=32)
+    m = models(b)
+    res = (64, 64, 64)
+    for mask in (1, 15):
+        BP = fa.decode(m, res, mask).double()
+        g = torch.randn_like(BP)
+        G = fa.decode_backward(m, res, g.float().contiguous(), mask).double()
+        lhs = (BP * g.double()).sum().item()
+        rhs = (m.ctrl.double() * G).sum().item()
+        assert abs(lhs - rhs) <= 1e-5 * (BP.abs() * g.abs()).sum().item(), (mask, lhs, rhs)
+
+
+def test_adjoint_leaves_padding(fa):
+    """Elements between lattices are not touched by the adjoint."""
+    b = mixed_batch(44, 5)
+    m = models(b)
+    res = (8, 8, 8)
+    g = torch.randn((5, 1) + res, device="cuda")
+    G = torch.full_like(m.ctrl, 7.0)
+    fa.decode_backward(m, res, g, 1, grad_ctrl=G)
+    G = G.cpu().numpy()
+    inside = np.zeros(G.size, bool)
+    for bb in range(5):
+        o = int(b.ctrl_off[bb])
+        inside[o:o + int(np.prod(b.ncp[bb]))] = True
+    assert np.all(G[~inside] == 7.0)
