@@ -96,10 +96,13 @@ typedef struct fa_work {
 /* Tunables of the batched decode (a0: batch plan and persistent schedule).
  * Zero fields take defaults. */
 typedef struct fa_tune {
-    int32_t rows_per_item; /* y rows per work item (multiple of waves)    */
-    int32_t waves;         /* waves (64 lanes) per workgroup, 1..16       */
-    int32_t grid;          /* persistent workgroups; 0 = one per item     */
-    int32_t kernel;        /* 0 = separable VALU, 1 = separable MFMA      */
+    int32_t rows_per_item; /* y rows per work item, 1..64 (default 8)           */
+    int32_t waves;         /* waves (64 lanes) per workgroup: 1, 2, 4, 8        */
+    int32_t grid;          /* persistent workgroups (capped at the item count)  */
+    int32_t kernel;        /* 0 = separable VALU, 1 = separable MFMA            */
+    int32_t slab_floats;   /* LDS lattice slab, 4096..16384 floats (default 8192);
+                              larger lattices are staged in x chunks            */
+    int32_t store;         /* 0 = non-temporal stores, 1 = ordinary stores      */
 } fa_tune;
 
 const char *fa_status_string(fa_status s);

@@ -40,7 +40,8 @@ assert WORK_DTYPE.itemsize == 12
 
 class FATune(ctypes.Structure):
     _fields_ = [("rows_per_item", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("slab_floats", ctypes.c_int32), ("store", ctypes.c_int32)]
 
 
 class FAError(RuntimeError):
@@ -179,8 +180,8 @@ class MicroModels:
 class Plan:
     """Host batch plan (fa_plan_decode) copied to the device."""
 
-    def __init__(self, models, res, rows=0, waves=0, grid=0, kernel=0):
-        self.tune = FATune(int(rows), int(waves), int(grid), int(kernel))
+    def __init__(self, models, res, rows=0, waves=0, grid=0, kernel=0, slab=0, store=0):
+        self.tune = FATune(int(rows), int(waves), int(grid), int(kernel), int(slab), int(store))
         cap = models.nblocks * ((int(res[1]) + 0) * ((int(res[2]) + 63) // 64))
         work = np.zeros(cap, WORK_DTYPE)
         off = np.zeros(cap + 1, np.int32)
@@ -208,7 +209,7 @@ def decode(models, res, mask=15, dtype="f32", plan=None, tune=None, out=None, st
         assert plan.res == tuple(int(r) for r in res)
         t, work, off, ng = plan.tune, _ptr(plan.work), _ptr(plan.wg_off), plan.ngroups
     else:
-        t = tune if tune is not None else FATune(0, 0, 0, 0)
+        t = tune if tune is not None else FATune(0, 0, 0, 0, 0, 0)
         work, off, ng = None, None, 0
     st = lib.fa_decode_blocks(_ptr(desc), models.nblocks, _ptr(models.knots), _ptr(ctrl),
                               DTYPES[dtype], _i32x3(res), int(mask), ctypes.byref(t), work, off,

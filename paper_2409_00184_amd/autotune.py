@@ -1,0 +1,117 @@
+"""Autotuner of the batched decode (row a0): tile and schedule search.
+
+For a batch of micro-models, a grid resolution, a channel mask and a
+lattice dtype it times every candidate (rows per work item, waves per
+workgroup, persistent grid size, kernel) through fa_plan_decode and
+fa_decode_blocks with HIP events, and keeps the fastest.  Results are
+cached in a JSON file keyed by a signature of the batch (histogram of NCP*
+and degree), so a later process with the same kind of batch skips the
+search.  Timing only chooses among schedules; every candidate computes the
+same result (the GPU tests check that schedules agree bit for bit).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import Plan, decode
+
+CACHE = os.environ.get("FA_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "fa_tune.json"))
+
+def _candidates():
+    out = []
+    for rows in (4, 8, 16):
+        for waves in (2, 4, 8):
+            if waves > rows:
+                continue
+            for grid in (512, 768, 1024, 1536, 2048, 1 << 20):
+                for slab in (4096, 6144, 8192):
+                    for store in (0, 1):
+                        out.append((rows, waves, grid, 0, slab, store))
+    return out
+
+
+# (rows per item, waves, persistent grid, kernel, LDS slab floats, store kind)
+CANDIDATES = _candidates()
+
+
+def signature(models, res, mask, dtype):
+    """Hash of the multiset of (NCP_x, NCP_y, NCP_z, degree) rows of the
+    batch, the resolution, mask, dtype and device name."""
+    d = models.host_desc
+    rows = np.concatenate([d["ncp"], d["degree"][:, :1]], axis=1).astype(np.int32)
+    uniq, cnt = np.unique(rows, axis=0, return_counts=True)
+    h = hashlib.sha1()
+    h.update(uniq.tobytes())
+    h.update(cnt.astype(np.int64).tobytes())
+    h.update(repr((tuple(int(r) for r in res), int(mask), dtype,
+                   torch.cuda.get_device_name())).encode())
+    return h.hexdigest()[:20]
+
+
+def _load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def time_plan(models, res, mask, dtype, plan, out, reps=5):
+    for _ in range(2):
+        decode(models, res, mask, dtype, plan=plan, out=out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        decode(models, res, mask, dtype, plan=plan, out=out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps
+
+
+def tune(models, res, mask=15, dtype="f32", candidates=None, use_cache=True, kernels=(0,),
+         verbose=False):
+    """Return (best Plan, report list of (candidate, ms))."""
+    sig = signature(models, res, mask, dtype)
+    cache = _load_cache() if use_cache else {}
+    if use_cache and sig in cache:
+        c = cache[sig]["best"]
+        return Plan(models, res, *c), [(tuple(c), cache[sig]["ms"])]
+    cands = [c for c in (candidates or CANDIDATES) if c[3] in kernels]
+    out = torch.empty((models.nblocks, bin(mask).count("1")) + tuple(res), dtype=torch.float32,
+                      device=models.device)
+    report = []
+    best = None
+    for c in cands:
+        try:
+            plan = Plan(models, res, *c)
+            ms = time_plan(models, res, mask, dtype, plan, out)
+        except RuntimeError as e:  # unsupported combination for this kernel
+            if verbose:
+                print("skip", c, e)
+            continue
+        report.append((c, ms))
+        if verbose:
+            print("tune", c, f"{ms:.4f} ms")
+        if best is None or ms < best[1]:
+            best = (c, ms, plan)
+    if best is None:
+        raise RuntimeError("no decode schedule candidate ran")
+    if use_cache:
+        cache[sig] = {"best": list(best[0]), "ms": best[1]}
+        _save_cache(cache)
+    return best[2], report

@@ -24,6 +24,8 @@ constexpr int kDefaultGrid = 768;  // 256 CUs x 3 resident workgroups (LDS bound
 
 int popcount4(uint32_t m) { return __builtin_popcount(m & 15u); }
 
+bool waves_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
 bool res_ok(const int32_t *res) {
     if (!res) return false;
     for (int a = 0; a < 3; ++a)
@@ -38,21 +40,28 @@ bool res_supported(const int32_t *res) {
 }
 
 struct Tune {
-    int rows, waves, grid, kernel;
+    int rows, waves, grid, kernel, slab, store;
 };
 
 Tune resolve(const fa_tune *t) {
-    Tune r{kDefaultRows, kDefaultWaves, 0, 0};
+    Tune r{kDefaultRows, kDefaultWaves, 0, 0, kSlabDefault, 0};
     if (t) {
         if (t->rows_per_item > 0) r.rows = t->rows_per_item;
         if (t->waves > 0) r.waves = t->waves;
         if (t->grid > 0) r.grid = t->grid;
         r.kernel = t->kernel;
+        if (t->slab_floats > 0) r.slab = t->slab_floats;
+        r.store = t->store;
     }
     return r;
 }
 
-bool waves_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+bool tune_ok(const Tune &t) {
+    return waves_ok(t.waves) && t.rows >= 1 && t.rows <= 64 && t.slab >= kSlabMin &&
+           t.slab <= kSlabMax && (t.store == 0 || t.store == 1) &&
+           (t.kernel == 0 || t.kernel == 1);
+}
+
 
 }  // namespace
 
@@ -118,7 +127,7 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
         return FA_ERR_INVALID_ARG;
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
-    if (!waves_ok(t.waves) || t.rows > 64) return FA_ERR_INVALID_ARG;
+    if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
     const int nrowt = (res[1] + t.rows - 1) / t.rows;
     const int ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
     const int64_t n = (int64_t)nblocks * nrowt * ncolt;
@@ -198,7 +207,7 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     if (work && ngroups <= 0) return FA_ERR_INVALID_ARG;
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
-    if (!waves_ok(t.waves) || t.rows > 64) return FA_ERR_INVALID_ARG;
+    if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
     DecodeLaunch a{};
     a.blocks = blocks;
     a.knots = knots;
@@ -215,13 +224,14 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     a.nrowt = (res[1] + t.rows - 1) / t.rows;
     a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
     a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
+    a.slab = t.slab;
+    a.nt_store = t.store == 0;
     a.out = out;
     int grid = work ? ngroups
                     : (int)std::min<int64_t>(a.nitems, t.grid > 0 ? t.grid : kDefaultGrid);
     hipError_t e;
     if (t.kernel == 1) e = launch_decode_mfma(a, t.waves, grid, (hipStream_t)stream);
-    else if (t.kernel == 0) e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
-    else return FA_ERR_INVALID_ARG;
+    else e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
     if (e == hipErrorNotSupported) return FA_ERR_UNSUPPORTED;
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }

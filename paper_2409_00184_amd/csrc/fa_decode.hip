@@ -27,13 +27,36 @@
 namespace fa {
 namespace {
 
+// Dynamic LDS of the separable decode: x table (rx rows), knots, slab.
 struct SepSmem {
-    float4 xB[kMaxRes];
-    float4 xD[kMaxRes];
-    int xS[kMaxRes];
-    float kn[kMaxKnotsPerBlock + 4];
-    float slab[kSlabFloats];
+    float4 *xB;
+    float4 *xD;
+    int *xS;
+    float *kn;
+    float *slab;
+    int slab_floats;
 };
+
+__device__ __forceinline__ SepSmem carve(void *base, int rx, int slab) {
+    SepSmem s;
+    char *p = static_cast<char *>(base);
+    s.xB = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * rx;
+    s.xD = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * rx;
+    s.kn = reinterpret_cast<float *>(p);
+    p += sizeof(float) * (kMaxKnotsPerBlock + 4);
+    s.xS = reinterpret_cast<int *>(p);
+    p += sizeof(int) * ((rx + 3) & ~3);
+    s.slab = reinterpret_cast<float *>(p);
+    s.slab_floats = slab;
+    return s;
+}
+
+__host__ __device__ size_t sep_lds_bytes(int rx, int slab) {
+    return sizeof(float4) * 2 * rx + sizeof(float) * (kMaxKnotsPerBlock + 4) +
+           sizeof(int) * ((rx + 3) & ~3) + sizeof(float) * slab;
+}
 
 template <int P>
 __device__ __forceinline__ float4 pack4(const float (&v)[P + 1]) {
@@ -49,7 +72,7 @@ __device__ __forceinline__ float comp(const float4 &v, int r) {
     return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
 }
 
-template <int P>
+template <int P, bool NT>
 __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0,
                          SepSmem &sm) {
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -82,7 +105,7 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     const int jlo = span_search(ny, P, ty, grid_pos(row0, a.ry)) - P;
     const int jhi = span_search(ny, P, ty, grid_pos(row0 + nrows - 1, a.ry));
     const int plane = (jhi - jlo + 1) * nz;  // slab floats per x plane
-    const int ic = min(nx, kSlabFloats / plane);
+    const int ic = min(nx, sm.slab_floats / plane);
     const bool single = (ic == nx);
 
     // z basis of this lane's column
@@ -200,18 +223,26 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
             }
             if (live) {
                 float *o = ob + (int64_t)u * plane_out;
-                if (a.mask & 1u) __builtin_nontemporal_store(val, o + choff[0]);
-                if (a.mask & 2u) __builtin_nontemporal_store(gx, o + choff[1]);
-                if (a.mask & 4u) __builtin_nontemporal_store(gy, o + choff[2]);
-                if (a.mask & 8u) __builtin_nontemporal_store(gz, o + choff[3]);
+                if (NT) {
+                    if (a.mask & 1u) __builtin_nontemporal_store(val, o + choff[0]);
+                    if (a.mask & 2u) __builtin_nontemporal_store(gx, o + choff[1]);
+                    if (a.mask & 4u) __builtin_nontemporal_store(gy, o + choff[2]);
+                    if (a.mask & 8u) __builtin_nontemporal_store(gz, o + choff[3]);
+                } else {
+                    if (a.mask & 1u) o[choff[0]] = val;
+                    if (a.mask & 2u) o[choff[1]] = gx;
+                    if (a.mask & 4u) o[choff[2]] = gy;
+                    if (a.mask & 8u) o[choff[3]] = gz;
+                }
             }
         }
     }
 }
 
-template <int WAVES>
+template <int WAVES, bool NT>
 __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) {
-    __shared__ SepSmem sm;
+    extern __shared__ float4 dyn_lds[];
+    SepSmem sm = carve(dyn_lds, a.rx, a.slab);
     int64_t beg, end, step;
     if (a.work) {
         beg = a.wg_off[blockIdx.x];
@@ -239,9 +270,9 @@ __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) 
             col0 = (r % a.ncolt) * kWave;
         }
         const int p = a.blocks[b].degree[0];
-        if (p == 3) sep_item<3>(a, b, row0, nrows, col0, sm);
-        else if (p == 2) sep_item<2>(a, b, row0, nrows, col0, sm);
-        else sep_item<1>(a, b, row0, nrows, col0, sm);
+        if (p == 3) sep_item<3, NT>(a, b, row0, nrows, col0, sm);
+        else if (p == 2) sep_item<2, NT>(a, b, row0, nrows, col0, sm);
+        else sep_item<1, NT>(a, b, row0, nrows, col0, sm);
     }
 }
 
@@ -311,14 +342,20 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(const fa_block *block
 
 }  // namespace
 
-hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
+template <bool NT>
+hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
+    const size_t lds = sep_lds_bytes(a.rx, a.slab);
     switch (waves) {
-    case 2: hipLaunchKernelGGL(decode_sep_kernel<2>, dim3(grid), dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(decode_sep_kernel<4>, dim3(grid), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(decode_sep_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
-    default: hipLaunchKernelGGL(decode_sep_kernel<1>, dim3(grid), dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT>), dim3(grid), dim3(128), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT>), dim3(grid), dim3(256), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((decode_sep_kernel<8, NT>), dim3(grid), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((decode_sep_kernel<1, NT>), dim3(grid), dim3(64), lds, s, a); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
+    return a.nt_store ? launch_sep<true>(a, waves, grid, s) : launch_sep<false>(a, waves, grid, s);
 }
 
 hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,

@@ -8,10 +8,11 @@
 
 namespace fa {
 
-// Fixed LDS budget of the separable decode (floats).
 constexpr int kWaveLanes = 64;
-constexpr int kSlabFloats = 8192;     // lattice slab
-constexpr int kMaxRes = FA_MAX_RES;   // x-table rows
+constexpr int kSlabDefault = 8192;  // LDS lattice slab of the separable decode (floats)
+constexpr int kSlabMin = 4096;      // >= NCP_y * NCP_z of any block: one x plane fits
+constexpr int kSlabMax = 16384;
+constexpr int kMaxRes = FA_MAX_RES;
 
 struct DecodeLaunch {
     const fa_block *blocks;
@@ -26,6 +27,8 @@ struct DecodeLaunch {
     int rows;                // rows per item in default order
     int nrowt, ncolt;        // tiles per block (default order)
     int64_t nitems;          // items in default order
+    int slab;                // LDS slab floats
+    int nt_store;            // 1: non-temporal stores
     float *out;
 };
 

@@ -103,7 +103,7 @@ def _plan(fa, d, res, rows, waves, grid):
     work = np.zeros(cap, fa.WORK_DTYPE)
     off = np.zeros(cap + 1, np.int32)
     nw, ng = ctypes.c_int64(), ctypes.c_int32()
-    t = fa.FATune(rows, waves, grid, 0)
+    t = fa.FATune(rows, waves, grid, 0, 0, 0)
     st = fa.lib.fa_plan_decode(d.ctypes.data, len(d), fa._i32x3(res), ctypes.byref(t),
                                work.ctypes.data, off.ctypes.data, cap, ctypes.byref(nw),
                                ctypes.byref(ng))

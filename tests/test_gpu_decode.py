@@ -62,7 +62,7 @@ def test_decode_tunings_agree(fa, rows, waves, grid):
     res = (21, 19, 66)
     ref = fa.decode(m, res, 15).cpu().numpy()
     out = fa.decode(m, res, 15, plan=fa.Plan(m, res, rows=rows, waves=waves, grid=grid))
-    out2 = fa.decode(m, res, 15, tune=fa.FATune(rows, waves, grid, 0))
+    out2 = fa.decode(m, res, 15, tune=fa.FATune(rows, waves, grid, 0, 4096, 1))
     assert np.array_equal(out.cpu().numpy(), ref), "schedule must not change results"
     assert np.array_equal(out2.cpu().numpy(), ref)
 
