@@ -128,6 +128,8 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
+    if (t.kernel == 1 && (t.rows != 4 || t.waves != 4 || res[2] > kWaveLanes))
+        return FA_ERR_UNSUPPORTED;
     const int nrowt = (res[1] + t.rows - 1) / t.rows;
     const int ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
     const int64_t n = (int64_t)nblocks * nrowt * ncolt;

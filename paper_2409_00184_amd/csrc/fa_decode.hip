@@ -345,6 +345,14 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(const fa_block *block
 template <bool NT>
 hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
     const size_t lds = sep_lds_bytes(a.rx, a.slab);
+    if (lds > 65536) {
+        const void *k = waves == 2 ? reinterpret_cast<const void *>(&decode_sep_kernel<2, NT>)
+                      : waves == 4 ? reinterpret_cast<const void *>(&decode_sep_kernel<4, NT>)
+                      : waves == 8 ? reinterpret_cast<const void *>(&decode_sep_kernel<8, NT>)
+                                   : reinterpret_cast<const void *>(&decode_sep_kernel<1, NT>);
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     switch (waves) {
     case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT>), dim3(grid), dim3(128), lds, s, a); break;
     case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT>), dim3(grid), dim3(256), lds, s, a); break;

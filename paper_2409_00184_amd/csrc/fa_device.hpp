@@ -83,6 +83,43 @@ __device__ __forceinline__ void basis_ders(KP t, int s, float u, float (&N)[P + 
     }
 }
 
+// Same as basis_ders<P> for a run-time degree p <= 3; entries beyond p are
+// zero.  One instantiation serves every degree (used where the window is
+// zero padded anyway, as in the dense matrix-core contraction).
+__device__ __forceinline__ void basis_ders_rt(const float *t, int s, float u, int p,
+                                              float (&N)[4], float (&D)[4]) {
+    float left[4] = {0, 0, 0, 0}, right[4] = {0, 0, 0, 0}, low[4] = {0, 0, 0, 0};
+    N[0] = 1.0f;
+    N[1] = N[2] = N[3] = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        if (k > p) break;
+        left[k] = u - t[s + 1 - k];
+        right[k] = t[s + k] - u;
+        if (k == p) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) low[r] = N[r];
+        }
+        float saved = 0.0f;
+#pragma unroll
+        for (int r = 0; r < k; ++r) {
+            float q = N[r] * rcp(right[r + 1] + left[k - r]);
+            N[r] = saved + right[r + 1] * q;
+            saved = left[k - r] * q;
+        }
+        N[k] = saved;
+    }
+#pragma unroll
+    for (int r = 0; r <= 3; ++r) {
+        float d = 0.0f;
+        if (r <= p) {
+            if (r >= 1) d += low[r - 1] * rcp(t[s + r] - t[s - p + r]);
+            if (r <= p - 1) d -= low[r] * rcp(t[s + r + 1] - t[s - p + r + 1]);
+        }
+        D[r] = float(p) * d;
+    }
+}
+
 // Grid position of voxel i on an axis of resolution R (FP32, correctly
 // rounded quotient; both sides of a parity check use this exact value).
 __device__ __forceinline__ float grid_pos(int i, int R) {

@@ -1,0 +1,164 @@
+"""BF16/FP16 lattices: per-block max-abs quantisation (bit-exact against a
+host reference) and the low-precision decodes (VALU kernel with 2-byte
+storage, MFMA kernel) against the FP64 oracle under an a-priori bound.
+
+Bound used (u = 2^-8 for BF16, 2^-11 for FP16, S = the oracle's
+sum |basis product| |P| of each output, which is the same for P and P/s
+up to the factor s that the kernels apply in FP32):
+  VALU, 2-byte storage: only P is rounded        -> |err| <= (u + 64 u32) S
+  MFMA: P, the x basis, the y-stage result and the z basis are rounded
+        (4 roundings; 6 allowed for second-order terms) -> (6 u + 64 u32) S
+"""
+import numpy as np
+import pytest
+import torch
+
+import fa_inputs as fi
+import oracle
+from gpu_util import U32, mixed_batch, models, oracle_blocks, say
+
+pytestmark = pytest.mark.gpu
+ULP = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+
+@pytest.fixture(scope="module")
+def fa():
+    import paper_2409_00184_amd as fa
+    assert torch.cuda.is_available()
+    return fa
+
+
+def host_quantize(b, dtype):
+    """Reference of fa_quantize_blocks: s = max|P| (1 if zero), q =
+    clamp(P * fl(1/s), -1, 1) in FP32, then RNE to the 2-byte type."""
+    codes = np.zeros(b.ctrl.size, np.uint16)
+    scales = np.zeros(b.nblocks, np.float32)
+    for k in range(b.nblocks):
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        P = b.ctrl[o:o + n].astype(np.float32)
+        s = np.float32(np.abs(P).max()) if np.abs(P).max() > 0 else np.float32(1.0)
+        inv = np.float32(1.0) / s
+        q = np.clip(P * inv, np.float32(-1), np.float32(1)).astype(np.float32)
+        if dtype == "bf16":
+            u = q.view(np.uint32).astype(np.uint64)
+            u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+            codes[o:o + n] = u.astype(np.uint16)
+        else:
+            codes[o:o + n] = q.astype(np.float16).view(np.uint16)
+        scales[k] = s
+    return codes, scales
+
+
+def dequant(b, codes, scales, dtype):
+    out = np.zeros(b.ctrl.size, np.float64)
+    if dtype == "bf16":
+        vals = (codes.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    else:
+        vals = codes.view(np.float16).astype(np.float64)
+    for k in range(b.nblocks):
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        out[o:o + n] = vals[o:o + n] * float(scales[k])
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_quantize_bit_exact(fa, dtype):
+    say("quantize", dtype)
+    b = mixed_batch(51, 20, ncp_hi=16)
+    b.ctrl[int(b.ctrl_off[3]):int(b.ctrl_off[3]) + int(np.prod(b.ncp[3]))] = 0.0  # zero block
+    m = models(b)
+    desc, lp = m.lattice(dtype)
+    codes, scales = host_quantize(b, dtype)
+    got = lp.cpu().numpy().view(np.uint16)
+    for k in range(b.nblocks):
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        assert np.array_equal(got[o:o + n], codes[o:o + n]), k
+    d = desc.cpu().numpy().view(fa.BLOCK_DTYPE)
+    assert np.array_equal(d["scale"], scales)
+    assert d["scale"][3] == 1.0
+
+
+def _bound_check(out, ref, S, c, u, what):
+    err = np.abs(out.astype(np.float64) - ref)
+    lim = (c * u + 64 * U32) * S + 1e-30
+    worst = float((err / lim).max())
+    assert worst <= 1.0, f"{what}: error {worst:.3f} x bound"
+    return worst
+
+
+def _decode_case(fa, b, res, dtype, kernel):
+    m = models(b)
+    if kernel == 1:
+        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1)
+    else:
+        plan = fa.Plan(m, res)
+    out = fa.decode(m, res, 15, dtype=dtype, plan=plan).cpu().numpy()
+    ob = oracle_blocks(b)
+    idx = np.array([[k, x, y, z] for k in range(b.nblocks) for x in range(res[0])
+                    for y in range(res[1]) for z in range(res[2])], np.int32)
+    ref, S = oracle.decode_samples(ob, res, idx, with_abs=True)
+    got = out.transpose(0, 2, 3, 4, 1).reshape(-1, 4)
+    c = 6.0 if kernel == 1 else 1.0
+    return _bound_check(got, ref, S, c, ULP[dtype], f"{dtype} kernel {kernel} {res}")
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("res", [(64, 64, 64), (23, 17, 41), (16, 5, 64)])
+def test_lowp_decode_bound(fa, kernel, dtype, res):
+    say("lowp decode", kernel, dtype, res)
+    b = mixed_batch(52, 10, ncp_lo=4, ncp_hi=32, nonuniform=0.3)
+    w = _decode_case(fa, b, res, dtype, kernel)
+    say("  worst / bound", w)
+
+
+def test_mfma_fallback_items(fa):
+    """Blocks the MFMA tile does not take (NCP > 32, wide y windows at a
+    small y resolution) go through the voxel-by-voxel path of the same
+    kernel and stay within the storage-rounding bound."""
+    say("mfma fallback")
+    g = fi.rng(53)
+    ncp = [(40, 8, 8), (8, 48, 12), (6, 6, 33), (32, 32, 32)]
+    deg = [(3, 3, 3), (2, 2, 2), (1, 1, 1), (3, 3, 3)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    b = fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+    for res in [(20, 6, 33), (64, 64, 64)]:
+        _decode_case(fa, b, res, "bf16", 1)
+
+
+def test_mfma_rejects_f32_and_bad_tiles(fa):
+    b = mixed_batch(54, 3)
+    m = models(b)
+    with pytest.raises(fa.FAError) as e:
+        fa.decode(m, (16, 16, 16), 15, dtype="f32", plan=fa.Plan(m, (16, 16, 16), 4, 4, 0, 1))
+    assert e.value.status == 2
+    with pytest.raises(fa.FAError) as e:
+        fa.Plan(m, (16, 16, 65), 4, 4, 0, 1)
+    assert e.value.status == 2
+
+
+def test_c5_sampled(fa):
+    """Config C5 (4096 blocks of 32^3 control points, k^-5/3 lattices, 64^3
+    voxels each, 1.07e9 voxels) in FP32 (VALU), BF16 and FP16 (MFMA):
+    errors on a 1% seeded sample against the FP64 oracle."""
+    say("C5")
+    b = fi.config_c5()
+    m = models(b)
+    res = (64, 64, 64)
+    g = fi.rng(55)
+    ns = 200_000
+    idx = np.stack([g.integers(0, b.nblocks, ns)] + [g.integers(0, 64, ns) for _ in range(3)],
+                   1).astype(np.int32)
+    ref, S = oracle.decode_samples(oracle_blocks(b), res, idx, with_abs=True)
+    ti = torch.as_tensor(idx, device="cuda").long()
+    out = torch.empty((b.nblocks, 4) + res, dtype=torch.float32, device="cuda")
+    for dtype, kernel in (("f32", 0), ("bf16", 1), ("f16", 1)):
+        plan = fa.Plan(m, res, rows=4, waves=4, kernel=kernel) if kernel else fa.Plan(m, res)
+        fa.decode(m, res, 15, dtype=dtype, plan=plan, out=out)
+        got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
+        if dtype == "f32":
+            err = np.abs(got - ref)
+            assert np.all(err <= 64 * U32 * S + 1e-30)
+        else:
+            _bound_check(got, ref, S, 6.0, ULP[dtype], f"C5 {dtype}")
+    del out
