@@ -187,16 +187,221 @@ def bench_c2(args):
         lp = {}
         for dt in ("bf16", "f16"):
             m.lattice(dt)
-            o2 = torch.empty_like(out)
-            g2, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dt, plan=plan, out=o2))
-            lms, lev, _ = timed_steps(g2.replay, args.steps, args.warmup, stream)
-            lp[dt] = {"value": nvox / (lms * 1e-3), "ms_per_step": lms,
-                      "speedup_vs_f32": ms / lms,
-                      "err_vs_fp64": err_vs_oracle_decode(batch, o2, res)}
-        line["lowp_storage"] = lp
+            for kern, pl in (("valu", plan), ("mfma", fa.Plan(m, res, rows=4, waves=4, kernel=1))):
+                o2 = torch.empty_like(out)
+                g2, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dt, plan=pl, out=o2))
+                lms, lev, _ = timed_steps(g2.replay, args.steps, args.warmup, stream)
+                lp[f"{dt}_{kern}"] = {"value": nvox / (lms * 1e-3), "ms_per_step": lms,
+                                      "speedup_vs_f32": ms / lms,
+                                      "err_vs_fp64": err_vs_oracle_decode(batch, o2, res)}
+                del o2, g2
+        line["lowp"] = lp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_decode(batch, res, args.cpu_seconds)
     return line
+
+
+def _common(args, metric, value, unit, ms, dtype, workload, extra):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": {"workload": workload}}
+    line.update(extra)
+    return line
+
+
+def _roof(alg_bytes, ev_ms, kernel, workload, bound="hbm"):
+    achieved = alg_bytes / (ev_ms * 1e-3) / 1e9
+    return {"bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kernel, workload),
+            "kernel": kernel, "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": ev_ms}
+
+
+# ------------------------------------------------------------------ C1
+
+def bench_c1(args):
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    from paper_2409_00184_amd import autotune
+    res = (64, 64, 64)
+    batch = fi.config_c1()
+    m = fa.MicroModels.from_batch(batch)
+    plan, _ = autotune.tune(m, res, 15, "f32", use_cache=not args.retune)
+    out = torch.empty((1, 4) + res, device="cuda")
+    graph, _ = fa.capture(lambda: fa.decode(m, res, 15, plan=plan, out=out))
+    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup,
+                               torch.cuda.current_stream())
+    nvox = 64 ** 3
+    line = _common(args, METRIC, nvox / (ms * 1e-3), "voxels/s", ms, "f32",
+                   "C1 single micro-model: 16^3 control points, cubic, decoded to 64^3 voxels "
+                   "(value + 3 gradients, FP32); latency-bound (one block)",
+                   {"roofline": _roof(nvox * 16 + 4 * 4096, ev_ms, "decode_sep", "c1"),
+                    "latency_us": ev_ms * 1e3,
+                    "err_vs_fp64": err_vs_oracle_decode(batch, out, res, src=batch.ctrl64)})
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_decode(batch, res, args.cpu_seconds)
+    return line
+
+
+# ------------------------------------------------------------------ C3
+
+def c3_samples(nx=1920, ny=1080, ns=512, seed=3):
+    """Ray-major FP32 sample positions of the seeded camera, built on the GPU
+    in chunks of rays (the same recipe as fa_inputs.ray_samples_np)."""
+    import torch
+
+    import fa_inputs as fi
+    o, d, t0, t1, j = fi.camera_rays(seed, nx, ny)
+    nray = o.shape[0]
+    f64 = dict(dtype=torch.float64, device="cuda")
+    O, D = torch.as_tensor(o, **f64), torch.as_tensor(d, **f64)
+    T0, T1, J = torch.as_tensor(t0, **f64), torch.as_tensor(t1, **f64), torch.as_tensor(j, **f64)
+    xyz = torch.empty((nray, ns, 3), dtype=torch.float32, device="cuda")
+    s = torch.arange(ns, **f64)
+    for r0 in range(0, nray, 1 << 18):
+        r1 = min(nray, r0 + (1 << 18))
+        t = T0[r0:r1, None] + (s[None] + J[r0:r1, None]) / ns * (T1 - T0)[r0:r1, None]
+        xyz[r0:r1] = (O[r0:r1, None] + D[r0:r1, None] * t[..., None]).float()
+    return xyz.reshape(-1, 3)
+
+
+def bench_c3(args):
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import oracle
+    import paper_2409_00184_amd as fa
+    b = fi.config_c3_blocks()
+    m = fa.MicroModels.from_batch(b)
+    xyz = c3_samples()
+    n = xyz.shape[0]
+    boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
+    out = torch.empty((n, 4), device="cuda")
+    run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
+    graph, _ = fa.capture(run)
+    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup,
+                               torch.cuda.current_stream())
+    g = np.random.Generator(np.random.PCG64(8))
+    idx = torch.as_tensor(g.integers(0, n, 200000), device="cuda")
+    xs = xyz[idx].cpu().numpy()
+    got = out[idx].double().cpu().numpy()
+    ob = oracle.Blocks(b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, b.ctrl)
+    ref = oracle.query_points(ob, xs, (16, 16, 16), (0, 0, 0), (1, 1, 1), fi.identity_cells(4096))
+    err = {k: float(np.abs(got[:, c] - ref[:, c]).max() / np.abs(ref[:, c]).max())
+           for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}
+    flops = 2 * 192 + 3 * 45  # contraction FMAs + basis/span work per sample (p = 3)
+    line = _common(args, "queried samples/sec (value+grad)", n / (ms * 1e-3), "samples/s", ms,
+                   "f32",
+                   "C3 ray-sample query: 1024^3 domain as 16^3 micro-models (NCP* per axis in "
+                   "8..32, cubic), 1920x1080 rays x 512 samples (1.06e9 non-grid positions), "
+                   "block lookup + span search + value + gradient, FP32",
+                   {"roofline": _roof(n * 28 + 4 * b.ctrl.size, ev_ms, "query", "c3"),
+                    "valu_tflops": n * flops / (ev_ms * 1e-3) / 1e12,
+                    "err_vs_fp64": err})
+    if not args.no_cpu_baseline:
+        th = oracle.nthreads_default()
+        t0 = time.perf_counter()
+        oracle.query_points(ob, xs[:20000], (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                            fi.identity_cells(4096), nthreads=th)
+        rate = 20000 / (time.perf_counter() - t0)
+        k = int(min(len(xs), max(20000, rate * args.cpu_seconds)))
+        t0 = time.perf_counter()
+        oracle.query_points(ob, xs[:k], (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                            fi.identity_cells(4096), nthreads=th)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": k / dt, "unit": "samples/s", "cores": th,
+                                "kind": "oracle",
+                                "sample": f"{k} seeded samples of the 1.06e9, FP64, {dt:.1f} s"}
+    del xyz, out
+    return line
+
+
+# ------------------------------------------------------------------ C4
+
+def bench_c4(args):
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    res = (64, 64, 64)
+    b, y = fi.config_c4()
+    m = fa.MicroModels.from_batch(b)
+    plan = fa.Plan(m, res)
+    yt = torch.as_tensor(y, device="cuda").reshape(b.nblocks, 1, *res)
+    ctrl = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([ctrl], lr=0.05)
+    losses = []
+
+    def it():
+        opt.zero_grad(set_to_none=False)
+        loss = ((fa.FADecode.apply(ctrl, m, res, 1, plan) - yt) ** 2).mean()
+        loss.backward()
+        opt.step()
+        return loss
+
+    stream = torch.cuda.current_stream()
+    ms, ev_ms, _ = timed_steps(lambda: losses.append(it()), args.steps, args.warmup, stream)
+    first, last = float(losses[0]), float(losses[-1])
+    # the two HIP kernels of an iteration, timed alone
+    out = torch.empty((b.nblocks, 1) + res, device="cuda")
+    gin = torch.randn_like(out)
+    G = torch.empty_like(m.ctrl)
+    fms, fev, _ = timed_steps(lambda: fa.decode(m, res, 1, plan=plan, out=out), 20, 3, stream)
+    bms, bev, _ = timed_steps(lambda: fa.decode_backward(m, res, gin, 1, grad_ctrl=G), 20, 3,
+                              stream)
+    nvox = b.nblocks * 64 ** 3
+    lat = 4 * int(sum(int(n.prod()) for n in b.ncp))
+    return _common(args, "fit iterations/sec (forward decode + MSE + HIP adjoint + Adam)",
+                   1e3 / ms, "iterations/s", ms, "f32",
+                   "C4 fit: 256 micro-models, NCP* per axis in {16,24,32}, cubic, 64^3 "
+                   "k^-5/3 samples each (67M), MSE through torch.autograd",
+                   {"roofline": _roof(nvox * 4 + lat, bev, "adjoint", "c4"),
+                    "forward_decode": {"ms": fev, "GB/s": (nvox * 4 + lat) / (fev * 1e-3) / 1e9},
+                    "adjoint": {"ms": bev, "GB/s": (nvox * 4 + lat) / (bev * 1e-3) / 1e9},
+                    "loss_first_last": [first, last]})
+
+
+# ------------------------------------------------------------------ C5
+
+def bench_c5(args):
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    res = (64, 64, 64)
+    b = fi.config_c5()
+    m = fa.MicroModels.from_batch(b)
+    nvox = b.nblocks * 64 ** 3
+    out = torch.empty((b.nblocks, 4) + res, device="cuda")
+    stream = torch.cuda.current_stream()
+    variants = {}
+    for name, dtype, kernel in (("f32_valu", "f32", 0), ("bf16_mfma", "bf16", 1),
+                                ("f16_mfma", "f16", 1), ("bf16_valu", "bf16", 0),
+                                ("f16_valu", "f16", 0)):
+        m.lattice(dtype)
+        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1) if kernel else fa.Plan(m, res, 4, 4,
+                                                                                1 << 20, 0,
+                                                                                8192, 1)
+        graph, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dtype, plan=plan, out=out))
+        ms, ev_ms, _ = timed_steps(graph.replay, max(5, args.steps // 5), 2, stream)
+        lat_b = (4 if dtype == "f32" else 2) * b.ctrl.size
+        variants[name] = {"value": nvox / (ms * 1e-3), "ms_per_step": ms,
+                          "roofline": _roof(nvox * 16 + lat_b, ev_ms,
+                                            "decode_mfma" if kernel else "decode_sep", "c5"),
+                          "err_vs_fp64": err_vs_oracle_decode(b, out, res, nsample=100000)}
+    base = variants["f32_valu"]["ms_per_step"]
+    for v in variants.values():
+        v["speedup_vs_f32"] = base / v["ms_per_step"]
+    best = variants["bf16_mfma"]
+    return _common(args, METRIC, best["value"], "voxels/s", best["ms_per_step"], "bf16",
+                   "C5 precision: 4096 micro-models of 32^3 control points (k^-5/3), cubic, "
+                   "64^3 voxels each (1.07e9), value + 3 gradients; BF16/FP16 lattices with "
+                   "per-block max-abs scale on MFMA (FP32 accumulation) vs FP32",
+                   {"roofline": best["roofline"], "variants": variants})
 
 
 def probe(args):
@@ -228,7 +433,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
@@ -252,7 +457,8 @@ def main():
     if args.probe:
         probe(args)
         return
-    line = {"c2": bench_c2}[args.workload](args)
+    line = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+            "c5": bench_c5}[args.workload](args)
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,162 @@
+"""Fitting control points through torch.autograd (C4), graph capture and the
+autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import fa_inputs as fi
+import oracle
+from gpu_util import U32, mixed_batch, models, oracle_blocks, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fa():
+    import paper_2409_00184_amd as fa
+    assert torch.cuda.is_available()
+    return fa
+
+
+def _fit_case(fa, b, y, P0, res):
+    m = models(b)
+    plan = fa.Plan(m, res)
+    ctrl = torch.as_tensor(P0, dtype=torch.float32, device="cuda").requires_grad_(True)
+    yt = torch.as_tensor(y, device="cuda").reshape(b.nblocks, 1, *res)
+    out = fa.FADecode.apply(ctrl, m, res, 1, plan)
+    loss = ((out - yt) ** 2).mean()
+    loss.backward()
+    return m, ctrl.grad.detach().cpu().numpy().astype(np.float64), float(loss)
+
+
+def _oracle_grad(b, P0, y, res):
+    """FP64: r = B P - y, grad = (2/M) B^T r, and (2/M) B^T |r| (its
+    rounding scale: the value basis is non-negative)."""
+    ob = oracle_blocks(b, P0.astype(np.float64))
+    f = oracle.decode_blocks(ob, res, 1)
+    r = f - y.reshape(f.shape).astype(np.float64)
+    M = r.size
+    g = oracle.decode_adjoint(ob, res, r, 1) * (2.0 / M)
+    ga = oracle.decode_adjoint(ob, res, np.abs(r), 1) * (2.0 / M)
+    return g, ga, float((r ** 2).mean()), f
+
+
+@pytest.mark.parametrize("nblocks,resn", [(6, 24), (256, 64)])
+def test_fit_gradient_vs_oracle_and_fd(fa, nblocks, resn):
+    """C4 shape at full size (256 blocks, 64^3 samples each, NCP* in
+    {16,24,32}, cubic, k^-5/3 targets) and a small case: the autograd
+    gradient (HIP adjoint) against the FP64 oracle gradient elementwise, and
+    against FP64 central differences (h = 1e-3) on 64 seeded control points."""
+    say("fit gradient", nblocks, resn)
+    b, y = fi.config_c4(nblocks=nblocks, res=resn)
+    res = (resn,) * 3
+    g = fi.rng(61)
+    P0 = (0.5 * g.normal(size=b.ctrl.size)).astype(np.float32)
+    m, grad, loss = _fit_case(fa, b, y, P0, res)
+    go, ga, lo, f = _oracle_grad(b, P0, y, res)
+    assert abs(loss - lo) <= 1e-5 * lo
+    valid = np.zeros(b.ctrl.size, bool)
+    for k in range(b.nblocks):
+        o = int(b.ctrl_off[k])
+        valid[o:o + int(np.prod(b.ncp[k]))] = True
+    err = np.abs(grad - go)[valid]
+    lim = 256 * U32 * ga[valid] + 1e-30
+    assert np.all(err <= lim), float((err / lim).max())
+    # central differences of the FP64 loss on 64 seeded control points
+    h = 1e-3
+    picks = g.choice(np.flatnonzero(valid), 64, replace=False)
+    ob = oracle_blocks(b, P0.astype(np.float64))
+    M = y.size
+    for e in picks:
+        k = int(np.searchsorted(b.ctrl_off, e, side="right") - 1)
+        sub = oracle.Blocks(ob.ncp[k:k + 1], ob.deg[k:k + 1], ob.knot_off[k:k + 1],
+                            ob.ctrl_off[k:k + 1], ob.knots, ob.ctrl)
+        yk = y[k].reshape(1, 1, *res).astype(np.float64)
+        Lk = []
+        for sgn in (1.0, -1.0):
+            c = ob.ctrl.copy()
+            c[e] += sgn * h
+            fk = oracle.decode_blocks(sub.with_ctrl(c), res, 1)
+            Lk.append(((fk - yk) ** 2).sum() / M)
+        fd = (Lk[0] - Lk[1]) / (2 * h)
+        assert abs(fd - grad[e]) <= 1e-4 * abs(fd) + 1e-3 * ga[e] + 1e-12, (e, fd, grad[e])
+
+
+def test_fit_converges(fa):
+    """A few Adam steps on C4-shaped blocks lower the loss steadily."""
+    say("fit converges")
+    b, y = fi.config_c4(nblocks=16, res=32)
+    res = (32, 32, 32)
+    m = models(b)
+    plan = fa.Plan(m, res)
+    ctrl = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
+    yt = torch.as_tensor(y, device="cuda").reshape(16, 1, *res)
+    opt = torch.optim.Adam([ctrl], lr=0.05)
+    losses = []
+    for it in range(40):
+        opt.zero_grad()
+        loss = ((fa.FADecode.apply(ctrl, m, res, 1, plan) - yt) ** 2).mean()
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    assert losses[-1] < 0.5 * losses[0], losses[::8]
+
+
+def test_graph_replay_matches_eager(fa):
+    """Decode (planned, persistent), query and adjoint captured into one
+    graph; every replay, with eager work and synchronisation in between,
+    reproduces the eager results bit for bit."""
+    say("graph replay")
+    b = mixed_batch(62, 12, ncp_hi=24)
+    m = models(b)
+    res = (20, 33, 40)
+    plan = fa.Plan(m, res, rows=4, waves=4, grid=37)
+    out = torch.empty((b.nblocks, 4) + res, device="cuda")
+    xyz = torch.rand(50000, 3, device="cuda")
+    boc = torch.arange(12, dtype=torch.int32, device="cuda")
+    q = torch.empty(50000, 4, device="cuda")
+    gin = torch.randn((b.nblocks, 1) + res, device="cuda")
+    G = torch.zeros_like(m.ctrl)
+
+    def step():
+        fa.decode(m, res, 15, plan=plan, out=out)
+        fa.query(m, xyz, (3, 2, 2), (0, 0, 0), (1, 1, 1), boc, out=q)
+        fa.decode_backward(m, res, gin, 1, grad_ctrl=G)
+
+    inside = torch.zeros(G.numel(), dtype=torch.bool)
+    for k in range(b.nblocks):
+        o = int(b.ctrl_off[k])
+        inside[o:o + int(np.prod(b.ncp[k]))] = True
+    inside = inside.cuda()
+    step()
+    torch.cuda.synchronize()
+    ref = (out.clone(), q.clone(), G.clone())
+    graph, _ = fa.capture(step)
+    for rep in range(5):
+        out.fill_(float("nan"))
+        q.zero_()
+        G.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref[0]), ("decode", rep)
+        assert torch.equal(q, ref[1]), ("query", rep)
+        assert torch.equal(G[inside], ref[2][inside]), ("adjoint", rep)
+        assert bool((G[~inside] == -1.0).all()), ("adjoint padding", rep)
+        _ = (out * 2).sum().item()  # eager work between replays
+
+
+def test_autotune_picks_valid_schedule(fa, tmp_path, monkeypatch):
+    say("autotune")
+    from paper_2409_00184_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    b = mixed_batch(63, 40, ncp_hi=32)
+    m = models(b)
+    res = (32, 32, 64)
+    plan, report = autotune.tune(m, res, 15, "f32", candidates=autotune.CANDIDATES[:6])
+    assert len(report) == 6 and (tmp_path / "tune.json").exists()
+    a = fa.decode(m, res, 15, plan=plan)
+    ref = fa.decode(m, res, 15)
+    assert torch.equal(a, ref)
+    plan2, rep2 = autotune.tune(m, res, 15, "f32")  # from the cache
+    assert len(rep2) == 1 and plan2.tune.rows_per_item == plan.tune.rows_per_item
