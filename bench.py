@@ -144,10 +144,13 @@ def bench_c2(args):
     batch = fi.config_c2()
     m = fa.MicroModels.from_batch(batch)
     stream = torch.cuda.current_stream()
-    plan, report = autotune.tune(m, res, 15, "f32", use_cache=not args.retune)
+    if args.tune:
+        plan, report = fa.Plan(m, res, *args.tune), [(tuple(args.tune), None)]
+    else:
+        plan, report = autotune.tune(m, res, 15, "f32", use_cache=not args.retune)
     log("schedule", [plan.tune.rows_per_item, plan.tune.waves, plan.ngroups,
                      plan.tune.slab_floats, plan.tune.store],
-        "fastest candidates", sorted(report, key=lambda r: r[1])[:6])
+        "fastest candidates", sorted(report, key=lambda r: r[1] or 0)[:6])
     out = torch.empty((batch.nblocks, 4) + res, dtype=torch.float32, device="cuda")
     graph, _ = fa.capture(lambda: fa.decode(m, res, 15, plan=plan, out=out))
     ms, ev_ms, ev_min = timed_steps(graph.replay, args.steps, args.warmup, stream)
@@ -280,7 +283,11 @@ def bench_c3(args):
     n = xyz.shape[0]
     boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
     out = torch.empty((n, 4), device="cuda")
-    run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
+    if args.ray_order:
+        run = lambda: fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0),
+                                    (1, 1, 1), boc, out=out)
+    else:
+        run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
     graph, _ = fa.capture(run)
     ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup,
                                torch.cuda.current_stream())
@@ -405,27 +412,51 @@ def bench_c5(args):
 
 
 def probe(args):
-    """Counter calibration run: a few plain launches of the workload's
-    dominant kernel and one device copy of exactly 1 GiB (the reference for
-    FETCH_SIZE / WRITE_SIZE scaling).  Prints what it ran."""
+    """Counter run: a few plain launches (no graph) of the workload's dominant
+    kernel, then one device copy of exactly 1 GiB each way (the reference for
+    scaling FETCH_SIZE / WRITE_SIZE).  Prints what it ran."""
     import torch
 
     import fa_inputs as fi
     import paper_2409_00184_amd as fa
     res = (64, 64, 64)
-    batch = fi.config_c2()
-    m = fa.MicroModels.from_batch(batch)
-    plan = fa.Plan(m, res, *args.probe_tune)
-    out = torch.empty((batch.nblocks, 4) + res, dtype=torch.float32, device="cuda")
+    w = args.workload
+    if w == "c3":
+        b = fi.config_c3_blocks()
+        m = fa.MicroModels.from_batch(b)
+        xyz = c3_samples()
+        boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
+        out = torch.empty((xyz.shape[0], 4), device="cuda")
+        run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
+    elif w == "c4":
+        b, _ = fi.config_c4()
+        m = fa.MicroModels.from_batch(b)
+        gin = torch.randn((b.nblocks, 1) + res, device="cuda")
+        G = torch.empty_like(m.ctrl)
+        run = lambda: fa.decode_backward(m, res, gin, 1, grad_ctrl=G)
+    elif w == "c5":
+        b = fi.config_c5()
+        m = fa.MicroModels.from_batch(b)
+        m.lattice("bf16")
+        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1)
+        out = torch.empty((b.nblocks, 4) + res, device="cuda")
+        run = lambda: fa.decode(m, res, 15, dtype="bf16", plan=plan, out=out)
+    else:
+        b = fi.config_c2() if w == "c2" else fi.config_c1()
+        m = fa.MicroModels.from_batch(b)
+        plan = fa.Plan(m, res, *args.probe_tune)
+        out = torch.empty((b.nblocks, 4) + res, device="cuda")
+        run = lambda: fa.decode(m, res, 15, plan=plan, out=out)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     for _ in range(args.steps):
-        fa.decode(m, res, 15, plan=plan, out=out)
+        run()
+    torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "c2", "decode_launches": args.steps,
-                      "copy_bytes_each_way": 1 << 30, "tune": list(args.probe_tune)}))
+    print(json.dumps({"probe": w, "launches": args.steps, "copy_bytes_each_way": 1 << 30,
+                      "tune": list(args.probe_tune)}))
 
 
 def main():
@@ -435,14 +466,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--tune", type=int, nargs=6, default=None,
+                    metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
+                    help="fixed decode schedule instead of the autotuner's")
+    ap.add_argument("--ray-order", action="store_true",
+                    help="C3: time fa_query_rays (8x8 ray tiles) instead of the flat order")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--probe", action="store_true",
                     help="counter calibration run (decode launches + a 1 GiB copy)")
-    ap.add_argument("--probe-tune", type=int, nargs=4, default=[8, 4, 768, 0],
-                    metavar=("ROWS", "WAVES", "GRID", "KERNEL"))
+    ap.add_argument("--probe-tune", type=int, nargs=6, default=[4, 4, 1 << 20, 0, 8192, 1],
+                    metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the decode "

@@ -198,6 +198,23 @@ fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
                           uint32_t mask, float *out, void *stream);
 
 /*
+ * Ray-structured point query: the same evaluation as fa_query_points for
+ * positions laid out as Alg. 4's pixel loop produces them, xyz =
+ * [height][width][samples][3] (ray-major, row-major pixels), out =
+ * [height][width][samples][4].  Results are identical to fa_query_points
+ * on the flattened arrays; only the order in which the GPU visits the
+ * samples differs (a wave takes an 8 x 8 tile of rays at the same sample
+ * index, where the lanes share micro-models and knot spans).
+ * Errors: FA_ERR_INVALID_ARG for width, height or samples <= 0, and as
+ * fa_query_points.
+ */
+fa_status fa_query_rays(const fa_block *blocks, int32_t nblocks, const int32_t *block_of_cell,
+                        const int32_t nb[3], const float origin[3], const float extent[3],
+                        const float *knots, const void *ctrl, fa_dtype dtype, const float *xyz,
+                        int32_t width, int32_t height, int32_t samples, uint32_t mask,
+                        float *out, void *stream);
+
+/*
  * Adjoint of the grid decode (row a7): grad_ctrl = B^T grad_out, where B
  * is the linear map ctrl -> decode output of fa_decode_blocks for the same
  * blocks, res and mask.  Deterministic (no atomics).

@@ -7,9 +7,9 @@ the binding raises.
 
 Entry points (same names as the C ABI):
   fa_validate_blocks, fa_plan_decode, fa_decode_blocks,
-  fa_decode_blocks_plain, fa_query_points, fa_decode_backward,
+  fa_decode_blocks_plain, fa_query_points, fa_query_rays, fa_decode_backward,
   fa_quantize_blocks
-and the conveniences MicroModels, Plan, decode, decode_plain, query,
+and the conveniences MicroModels, Plan, decode, decode_plain, query, query_rays,
 decode_backward, FADecode (torch.autograd.Function), capture.
 """
 import ctypes
@@ -19,7 +19,8 @@ import numpy as np
 import torch
 
 __all__ = ["FA_F32", "FA_BF16", "FA_F16", "BLOCK_DTYPE", "WORK_DTYPE", "FAError", "lib",
-           "MicroModels", "Plan", "decode", "decode_plain", "query", "decode_backward",
+           "MicroModels", "Plan", "decode", "decode_plain", "query", "query_rays",
+           "decode_backward",
            "FADecode", "capture", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,6 +77,9 @@ def _load():
     L.fa_query_points.restype = ctypes.c_int
     L.fa_query_points.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, u32,
                                   vp, vp]
+    L.fa_query_rays.restype = ctypes.c_int
+    L.fa_query_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32, i32,
+                                u32, vp, vp]
     L.fa_decode_backward.restype = ctypes.c_int
     L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
     L.fa_quantize_blocks.restype = ctypes.c_int
@@ -243,6 +247,23 @@ def query(models, xyz, nb, origin, extent, block_of_cell, mask=15, dtype="f32", 
                              DTYPES[dtype], _ptr(xyz), n, int(mask), _ptr(out),
                              _stream(stream))
     _check("fa_query_points", st)
+    return out
+
+
+def query_rays(models, xyz, width, height, samples, nb, origin, extent, block_of_cell,
+               mask=15, dtype="f32", out=None, stream=None):
+    """Ray-structured query (fa_query_rays): xyz [height*width*samples, 3]
+    ray-major -> [height*width*samples, 4]; same values as query()."""
+    desc, ctrl = models.lattice(dtype, stream)
+    n = int(width) * int(height) * int(samples)
+    assert xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.numel() == 3 * n
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=models.device)
+    st = lib.fa_query_rays(_ptr(desc), models.nblocks, _ptr(block_of_cell), _i32x3(nb),
+                           _f32x3(origin), _f32x3(extent), _ptr(models.knots), _ptr(ctrl),
+                           DTYPES[dtype], _ptr(xyz), int(width), int(height), int(samples),
+                           int(mask), _ptr(out), _stream(stream))
+    _check("fa_query_rays", st)
     return out
 
 

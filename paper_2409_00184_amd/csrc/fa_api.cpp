@@ -250,11 +250,14 @@ fa_status fa_decode_blocks_plain(const fa_block *blocks, int32_t nblocks, const 
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
-fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
-                          const int32_t *block_of_cell, const int32_t nb[3],
-                          const float origin[3], const float extent[3], const float *knots,
-                          const void *ctrl, fa_dtype dtype, const float *xyz, int64_t n,
-                          uint32_t mask, float *out, void *stream) {
+}  // extern "C"
+
+namespace {
+fa_status query_common(const fa_block *blocks, int32_t nblocks, const int32_t *block_of_cell,
+                       const int32_t nb[3], const float origin[3], const float extent[3],
+                       const float *knots, const void *ctrl, fa_dtype dtype, const float *xyz,
+                       int64_t n, uint32_t mask, float *out, int rw, int rh, int rk,
+                       void *stream) {
     if (!blocks || nblocks <= 0 || !block_of_cell || !nb || !origin || !extent || !knots ||
         !ctrl || n < 0 || (n > 0 && (!xyz || !out)) || (mask & 15u) == 0 ||
         (mask & ~15u) != 0)
@@ -280,8 +283,34 @@ fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
     a.n = n;
     a.mask = mask;
     a.out = out;
+    a.rw = rw;
+    a.rh = rh;
+    a.rk = rk;
     hipError_t e = launch_query(a, (hipStream_t)stream);
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+}  // namespace
+
+extern "C" {
+
+fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
+                          const int32_t *block_of_cell, const int32_t nb[3],
+                          const float origin[3], const float extent[3], const float *knots,
+                          const void *ctrl, fa_dtype dtype, const float *xyz, int64_t n,
+                          uint32_t mask, float *out, void *stream) {
+    return query_common(blocks, nblocks, block_of_cell, nb, origin, extent, knots, ctrl, dtype,
+                        xyz, n, mask, out, 0, 0, 0, stream);
+}
+
+fa_status fa_query_rays(const fa_block *blocks, int32_t nblocks, const int32_t *block_of_cell,
+                        const int32_t nb[3], const float origin[3], const float extent[3],
+                        const float *knots, const void *ctrl, fa_dtype dtype, const float *xyz,
+                        int32_t width, int32_t height, int32_t samples, uint32_t mask,
+                        float *out, void *stream) {
+    if (width <= 0 || height <= 0 || samples <= 0) return FA_ERR_INVALID_ARG;
+    return query_common(blocks, nblocks, block_of_cell, nb, origin, extent, knots, ctrl, dtype,
+                        xyz, (int64_t)width * height * samples, mask, out, width, height,
+                        samples, stream);
 }
 
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,

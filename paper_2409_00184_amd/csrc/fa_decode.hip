@@ -243,13 +243,14 @@ template <int WAVES, bool NT>
 __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) {
     extern __shared__ float4 dyn_lds[];
     SepSmem sm = carve(dyn_lds, a.rx, a.slab);
+    const int wg = xcd_order(blockIdx.x, gridDim.x);
     int64_t beg, end, step;
     if (a.work) {
-        beg = a.wg_off[blockIdx.x];
-        end = a.wg_off[blockIdx.x + 1];
+        beg = a.wg_off[wg];
+        end = a.wg_off[wg + 1];
         step = 1;
     } else {
-        beg = blockIdx.x;
+        beg = wg;
         end = a.nitems;
         step = gridDim.x;
     }

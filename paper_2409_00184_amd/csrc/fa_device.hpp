@@ -83,6 +83,40 @@ __device__ __forceinline__ void basis_ders(KP t, int s, float u, float (&N)[P + 
     }
 }
 
+// basis_ders<P> on a knot window held in registers: tw[m] = t[s-P+1+m],
+// m = 0..2P-1 (every knot the p+1 non-zero functions and their
+// derivatives touch), so all indices are compile-time constants.
+template <int P>
+__device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u,
+                                               float (&N)[P + 1], float (&D)[P + 1]) {
+    float left[P + 1], right[P + 1], low[P + 1];
+    N[0] = 1.0f;
+#pragma unroll
+    for (int k = 1; k <= P; ++k) {
+        left[k] = u - tw[P - k];       // t[s+1-k]
+        right[k] = tw[P - 1 + k] - u;  // t[s+k]
+        if (k == P) {
+#pragma unroll
+            for (int r = 0; r < P; ++r) low[r] = N[r];
+        }
+        float saved = 0.0f;
+#pragma unroll
+        for (int r = 0; r < k; ++r) {
+            float q = N[r] * rcp(right[r + 1] + left[k - r]);
+            N[r] = saved + right[r + 1] * q;
+            saved = left[k - r] * q;
+        }
+        N[k] = saved;
+    }
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+        float d = 0.0f;
+        if (r >= 1) d += low[r - 1] * rcp(tw[P - 1 + r] - tw[r - 1]);  // t[s+r] - t[s-P+r]
+        if (r <= P - 1) d -= low[r] * rcp(tw[P + r] - tw[r]);          // t[s+r+1] - t[s-P+r+1]
+        D[r] = float(P) * d;
+    }
+}
+
 // Same as basis_ders<P> for a run-time degree p <= 3; entries beyond p are
 // zero.  One instantiation serves every degree (used where the window is
 // zero padded anyway, as in the dense matrix-core contraction).
@@ -118,6 +152,20 @@ __device__ __forceinline__ void basis_ders_rt(const float *t, int s, float u, in
         }
         D[r] = float(p) * d;
     }
+}
+
+// XCD-aware workgroup order.  The dispatcher deals workgroups round-robin
+// over the 8 XCDs (workgroup b runs on XCD b % 8), each with its own L2.
+// This maps b to a logical index so that the workgroups one XCD runs are
+// consecutive logical indices; when consecutive indices touch neighbouring
+// data, each XCD's L2 then holds one compact region instead of a share of
+// everything.  A permutation of [0, n) for any n.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_order(int b, int n) {
+    const int q = n / kXcds, r = n % kXcds;  // XCD x runs q + (x < r) workgroups
+    const int x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
 }
 
 // Grid position of voxel i on an axis of resolution R (FP32, correctly

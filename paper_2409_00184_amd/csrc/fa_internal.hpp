@@ -52,6 +52,8 @@ struct QueryLaunch {
     int64_t n;
     uint32_t mask;
     float *out;
+    // ray-structured order (0 = flat list): positions are [rh][rw][rk]
+    int rw, rh, rk;
 };
 
 hipError_t launch_query(const QueryLaunch &a, hipStream_t s);

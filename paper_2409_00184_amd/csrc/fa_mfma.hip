@@ -43,6 +43,7 @@ constexpr int kUC = 16;      // x voxels per chunk
 constexpr int kK = 32;       // MFMA K (NCP padded)
 constexpr int kPtStride = 40;  // halfs per (j,k) row of the transposed slab
 constexpr int kR2Stride = 40;  // halfs per (u,v) row of R2
+constexpr int kStageStride = 68;  // floats per staged output row (64 + 4: no bank conflicts)
 
 __device__ __forceinline__ uint16_t to_bits(float x, bool bf) {
     if (bf) {
@@ -287,33 +288,42 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
             }
         }
         __syncthreads();
-        // z stage: wave q owns R2 rows 16q..16q+15 = x voxels u0+4q..u0+4q+3, 4 rows
+        // z stage: wave q owns R2 rows 16q..16q+15 = x voxels u0+4q..u0+4q+3,
+        // 4 rows.  Each channel's 4 x 4 x 64 tile goes through this wave's
+        // LDS region (the R1 buffer, dead until the next chunk) so every
+        // global store writes one whole 256-byte z row.
         {
             const int row = 16 * wave + l16;
             const u16x8 aBB = *reinterpret_cast<const u16x8 *>(R2 + (0 * kUC * kRows + row) * kR2Stride + 8 * g);
             const u16x8 aDB = *reinterpret_cast<const u16x8 *>(R2 + (1 * kUC * kRows + row) * kR2Stride + 8 * g);
             const u16x8 aBD = *reinterpret_cast<const u16x8 *>(R2 + (2 * kUC * kRows + row) * kR2Stride + 8 * g);
-            const int u = u0 + 4 * wave + g;  // output rows of this lane: u, v = row0 + r
-            const bool uok = u < a.rx;
+            float *stage = R1B + wave * (16 * kStageStride);
+            const int w = col0 + lane;
+            for (int ch = 0; ch < 4; ++ch) {
+                if (!((a.mask >> ch) & 1u)) continue;
+                const u16x8 &aa = ch == 1 ? aDB : (ch == 2 ? aBD : aBB);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
-                const f32x4v val = mfma(aBB, fBz[nt], z, bf);
-                const f32x4v gdz = mfma(aBB, fDz[nt], z, bf);
-                const f32x4v gdx = mfma(aDB, fBz[nt], z, bf);
-                const f32x4v gdy = mfma(aBD, fBz[nt], z, bf);
-                __builtin_amdgcn_sched_barrier(0);
-                const int w = col0 + 16 * nt + l16;
-                if (!uok || w >= a.rz) continue;
+                for (int nt = 0; nt < 4; ++nt) {
+                    const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
+                    const f32x4v d = mfma(aa, ch == 3 ? fDz[nt] : fBz[nt], z, bf);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (r >= nrows) break;
-                    float *o = ob + (int64_t)u * plane + (int64_t)(row0 + r) * a.rz + w;
-                    if (a.mask & 1u) o[choff[0]] = val[r] * scale;
-                    if (a.mask & 2u) o[choff[1]] = gdx[r] * scale;
-                    if (a.mask & 4u) o[choff[2]] = gdy[r] * scale;
-                    if (a.mask & 8u) o[choff[3]] = gdz[r] * scale;
+                    for (int r = 0; r < 4; ++r)
+                        stage[(4 * g + r) * kStageStride + 16 * nt + l16] = d[r] * scale;
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                float *oc = ob + choff[ch];
+#pragma unroll 4
+                for (int rr = 0; rr < 16; ++rr) {
+                    const int u = u0 + 4 * wave + (rr >> 2), v = row0 + (rr & 3);
+                    const float val = stage[rr * kStageStride + lane];
+                    if (u < a.rx && (rr & 3) < nrows && w < a.rz)
+                        oc[(int64_t)u * plane + (int64_t)v * a.rz + w] = val;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
         __syncthreads();  // R1/R2 reused by the next chunk
@@ -324,13 +334,14 @@ __global__ __launch_bounds__(256, 2) void decode_mfma_kernel(MfmaArgs A) {
     extern __shared__ float4 dyn_lds[];
     char *lds = reinterpret_cast<char *>(dyn_lds);
     const DecodeLaunch &a = A.d;
+    const int wg = xcd_order(blockIdx.x, gridDim.x);
     int64_t beg, end, step;
     if (a.work) {
-        beg = a.wg_off[blockIdx.x];
-        end = a.wg_off[blockIdx.x + 1];
+        beg = a.wg_off[wg];
+        end = a.wg_off[wg + 1];
         step = 1;
     } else {
-        beg = blockIdx.x;
+        beg = wg;
         end = a.nitems;
         step = gridDim.x;
     }

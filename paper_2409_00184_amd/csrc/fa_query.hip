@@ -2,12 +2,18 @@
 //
 // Alg. 4 evaluates valueMicroModel and gradientMicroModel at every ray
 // sample.  One lane per sample, grid-stride over the samples (which arrive
-// ray-major, so the lanes of a wave walk one ray and mostly share a block):
-//   a1  block lookup in FP32 (one rounding per operation, see fa.h);
-//   a2  span per axis: for knots flagged uniform, a guess p + floor(u(n-p))
-//       corrected against the stored knots, else a binary search;
-//   a3  FP32 basis and first derivative (triangular de Boor form);
-//   a4  the (p+1)^3 control window, z-runs of p+1 consecutive points;
+// ray-major, so the 64 lanes of a wave walk one ray and mostly share a
+// micro-model):
+//   a1  block lookup in FP32 (one rounding per operation, see fa.h); when
+//       every lane of the wave is in the same block the descriptor is read
+//       once with scalar loads;
+//   a2  span per axis: for knots flagged uniform, the guess p + floor(u(n-p))
+//       is corrected by one comparison each way against the stored knots,
+//       which arrive with the whole knot window in two vector loads; other
+//       knot vectors take a binary search;
+//   a3  FP32 basis and first derivative on the register knot window;
+//   a4  the (p+1)^3 control window as (p+1)^2 vector loads of p+1
+//       consecutive z points (served by L1/L2: neighbouring lanes overlap);
 //   a5  separable contraction of the window: z, then y, then x;
 //   a6  chain rule d/dx = r d/du and one 16-byte store per sample.
 #include "fa_device.hpp"
@@ -16,44 +22,83 @@
 namespace fa {
 namespace {
 
-template <int P>
-__device__ __forceinline__ int axis_span(int n, const float *t, float u, bool uniform) {
-    if (uniform) return span_from_guess(n, P, t, u, P + (int)(u * float(n - P)));
-    return span_search(n, P, t, u);
+template <int N>
+struct Vec {
+    float v[N];
+};
+
+// N consecutive floats from a 4-byte aligned address as one vector load
+// (gfx950 accepts dword-aligned multi-dword global loads).
+template <int N>
+__device__ __forceinline__ Vec<N> ldv(const float *p) {
+    Vec<N> r;
+    __builtin_memcpy(&r, p, sizeof(r));
+    return r;
 }
 
+// Span and register knot window tw[m] = t[s-P+1+m] of one axis.
 template <int P>
-__device__ __forceinline__ float4 query_block(const QueryLaunch &a, const fa_block &B,
+__device__ __forceinline__ int axis_window(int n, const float *t, float u, bool uniform,
+                                           float (&tw)[2 * P]) {
+    if (uniform) {
+        int s0 = P + (int)(u * float(n - P));
+        s0 = s0 > n - 1 ? n - 1 : s0;
+        // t[s0-P .. s0+P+1]: covers the windows of s0-1, s0, s0+1
+        const Vec<2 * P + 2> w = ldv<2 * P + 2>(t + s0 - P);
+        int d = 0;
+        if (s0 > P && u < w.v[P]) d = -1;                   // u < t[s0]
+        else if (s0 < n - 1 && u >= w.v[P + 1]) d = 1;      // u >= t[s0+1]
+#pragma unroll
+        for (int m = 0; m < 2 * P; ++m)
+            tw[m] = d < 0 ? w.v[m] : (d > 0 ? w.v[m + 2] : w.v[m + 1]);
+        return s0 + d;
+    }
+    const int s = span_search(n, P, t, u);
+    const Vec<2 * P> w = ldv<2 * P>(t + s - P + 1);
+#pragma unroll
+    for (int m = 0; m < 2 * P; ++m) tw[m] = w.v[m];
+    return s;
+}
+
+struct BlockView {
+    int nx, ny, nz;
+    uint32_t flags;
+    int64_t knot_off, ctrl_off;
+    float scale;
+};
+
+template <int P, int DT>
+__device__ __forceinline__ float4 query_block(const QueryLaunch &a, const BlockView &B,
                                               const float (&uu)[3]) {
-    const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
-    const uint32_t fl = B.flags;
     const float *tx = a.knots + B.knot_off;
-    const float *ty = tx + nx + P + 1;
-    const float *tz = ty + ny + P + 1;
-    const int sx = axis_span<P>(nx, tx, uu[0], fl & FA_FLAG_UNIFORM_X);
-    const int sy = axis_span<P>(ny, ty, uu[1], fl & FA_FLAG_UNIFORM_Y);
-    const int sz = axis_span<P>(nz, tz, uu[2], fl & FA_FLAG_UNIFORM_Z);
+    const float *ty = tx + B.nx + P + 1;
+    const float *tz = ty + B.ny + P + 1;
+    float wx[2 * P], wy[2 * P], wz[2 * P];
+    const int sx = axis_window<P>(B.nx, tx, uu[0], B.flags & FA_FLAG_UNIFORM_X, wx);
+    const int sy = axis_window<P>(B.ny, ty, uu[1], B.flags & FA_FLAG_UNIFORM_Y, wy);
+    const int sz = axis_window<P>(B.nz, tz, uu[2], B.flags & FA_FLAG_UNIFORM_Z, wz);
     float xB[P + 1], xD[P + 1], yB[P + 1], yD[P + 1], zB[P + 1], zD[P + 1];
-    basis_ders<P>(tx, sx, uu[0], xB, xD);
-    basis_ders<P>(ty, sy, uu[1], yB, yD);
-    basis_ders<P>(tz, sz, uu[2], zB, zD);
-    const int64_t base = B.ctrl_off + ((int64_t)(sx - P) * ny + (sy - P)) * nz + (sz - P);
-    const float scale = B.scale;
+    basis_ders_win<P>(wx, uu[0], xB, xD);
+    basis_ders_win<P>(wy, uu[1], yB, yD);
+    basis_ders_win<P>(wz, uu[2], zB, zD);
+    const int64_t base = B.ctrl_off + ((int64_t)(sx - P) * B.ny + (sy - P)) * B.nz + (sz - P);
     float f = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
 #pragma unroll
     for (int i = 0; i <= P; ++i) {
         float uBB = 0.0f, uDB = 0.0f, uBD = 0.0f;
 #pragma unroll
         for (int j = 0; j <= P; ++j) {
-            const int64_t row = base + ((int64_t)i * ny + j) * nz;
+            const int64_t row = base + ((int64_t)i * B.ny + j) * B.nz;
             float c[P + 1];
-            if (a.dtype == FA_F32) {
-                const float *cp = static_cast<const float *>(a.ctrl) + row;
+            if (DT == FA_F32) {
+                const Vec<P + 1> r = ldv<P + 1>(static_cast<const float *>(a.ctrl) + row);
 #pragma unroll
-                for (int k = 0; k <= P; ++k) c[k] = cp[k];
+                for (int k = 0; k <= P; ++k) c[k] = r.v[k];
             } else {
+                const uint16_t *h = static_cast<const uint16_t *>(a.ctrl) + row;
 #pragma unroll
-                for (int k = 0; k <= P; ++k) c[k] = load_ctrl(a.ctrl, a.dtype, row + k, scale);
+                for (int k = 0; k <= P; ++k)
+                    c[k] = (DT == FA_BF16 ? bf16_to_f32(h[k]) : f16_to_f32(h[k]));
             }
             float tB = 0.0f, tD = 0.0f;
 #pragma unroll
@@ -70,7 +115,8 @@ __device__ __forceinline__ float4 query_block(const QueryLaunch &a, const fa_blo
         fy = fmaf(xB[i], uDB, fy);
         fz = fmaf(xB[i], uBD, fz);
     }
-    return make_float4(f, fx, fy, fz);
+    const float s = DT == FA_F32 ? 1.0f : B.scale;
+    return make_float4(f * s, fx * s, fy * s, fz * s);
 }
 
 // Block lookup in FP32 with no fused operations: the block index is an
@@ -87,32 +133,106 @@ __device__ __forceinline__ int lookup_axis(float x, float origin, float r, int n
     return b;
 }
 
+__device__ __forceinline__ BlockView view_of(const fa_block &B) {
+    BlockView v;
+    v.nx = B.ncp[0];
+    v.ny = B.ncp[1];
+    v.nz = B.ncp[2];
+    v.flags = B.flags;
+    v.knot_off = B.knot_off;
+    v.ctrl_off = B.ctrl_off;
+    v.scale = B.scale;
+    return v;
+}
+
+template <int DT>
+__device__ __forceinline__ float4 query_any(const QueryLaunch &a, const BlockView &V, int p,
+                                            const float (&uu)[3]) {
+    if (p == 3) return query_block<3, DT>(a, V, uu);
+    if (p == 2) return query_block<2, DT>(a, V, uu);
+    return query_block<1, DT>(a, V, uu);
+}
+
+// One sample for every lane of the wave; `live` false makes the lane an
+// empty sample that still takes part in the wave-wide votes.
+template <int DT>
+__device__ __forceinline__ void query_sample(const QueryLaunch &a, int64_t q, bool live) {
+    float x = 0.0f, y = 0.0f, z = 0.0f;
+    if (live) {
+        const Vec<3> p3 = ldv<3>(a.xyz + 3 * q);
+        x = p3.v[0];
+        y = p3.v[1];
+        z = p3.v[2];
+    }
+    float uu[3];
+    const int bx = lookup_axis(x, a.origin[0], a.rscale[0], a.nb[0], uu[0]);
+    const int by = lookup_axis(y, a.origin[1], a.rscale[1], a.nb[1], uu[1]);
+    const int bz = lookup_axis(z, a.origin[2], a.rscale[2], a.nb[2], uu[2]);
+    int blk = live ? a.block_of_cell[(bx * a.nb[1] + by) * a.nb[2] + bz] : -1;
+    if (blk >= a.nblocks) blk = -1;  // anything outside [0, nblocks) is an empty cell
+    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int blk0 = __builtin_amdgcn_readfirstlane(blk);
+    if (__all(blk == blk0)) {
+        // wave-uniform block: scalar descriptor loads, no divergence
+        if (blk0 >= 0) {
+            const fa_block &B = a.blocks[blk0];
+            r = query_any<DT>(a, view_of(B), B.degree[0], uu);
+        }
+    } else if (blk >= 0) {
+        const fa_block &B = a.blocks[blk];
+        r = query_any<DT>(a, view_of(B), B.degree[0], uu);
+    }
+    if (!live) return;
+    r.y *= a.rscale[0];
+    r.z *= a.rscale[1];
+    r.w *= a.rscale[2];
+    if (!(a.mask & 1u)) r.x = 0.0f;
+    if (!(a.mask & 2u)) r.y = 0.0f;
+    if (!(a.mask & 4u)) r.z = 0.0f;
+    if (!(a.mask & 8u)) r.w = 0.0f;
+    const f32x4 rv = {r.x, r.y, r.z, r.w};
+    __builtin_nontemporal_store(rv, reinterpret_cast<f32x4 *>(a.out) + q);
+}
+
+// Flat list: lanes take consecutive samples.
+template <int DT>
 __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n; q += stride) {
-        const float x = a.xyz[3 * q], y = a.xyz[3 * q + 1], z = a.xyz[3 * q + 2];
-        float uu[3];
-        const int bx = lookup_axis(x, a.origin[0], a.rscale[0], a.nb[0], uu[0]);
-        const int by = lookup_axis(y, a.origin[1], a.rscale[1], a.nb[1], uu[1]);
-        const int bz = lookup_axis(z, a.origin[2], a.rscale[2], a.nb[2], uu[2]);
-        const int blk = a.block_of_cell[(bx * a.nb[1] + by) * a.nb[2] + bz];
-        float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (blk >= 0 && blk < a.nblocks) {  // anything else is an empty cell
-            const fa_block &B = a.blocks[blk];
-            const int p = B.degree[0];
-            if (p == 3) r = query_block<3>(a, B, uu);
-            else if (p == 2) r = query_block<2>(a, B, uu);
-            else r = query_block<1>(a, B, uu);
-            r.y *= a.rscale[0];
-            r.z *= a.rscale[1];
-            r.w *= a.rscale[2];
-        }
-        if (!(a.mask & 1u)) r.x = 0.0f;
-        if (!(a.mask & 2u)) r.y = 0.0f;
-        if (!(a.mask & 4u)) r.z = 0.0f;
-        if (!(a.mask & 8u)) r.w = 0.0f;
-        const f32x4 rv = {r.x, r.y, r.z, r.w};
-        __builtin_nontemporal_store(rv, reinterpret_cast<f32x4 *>(a.out) + q);
+    // every lane runs the same trip count, so the wave-wide votes see all
+    // 64 lanes (lanes past the end take part as empty samples)
+    const int64_t n_round = (a.n + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int wg = xcd_order(blockIdx.x, gridDim.x);
+    for (int64_t q = (int64_t)wg * blockDim.x + threadIdx.x; q < n_round; q += stride)
+        query_sample<DT>(a, q, q < a.n);
+}
+
+// Ray-structured: a wave owns an 8 x 8 tile of rays and walks a chunk of
+// kRayChunk sample indices; at one sample index the 64 lanes sit within a
+// pixel footprint of each other (usually one micro-model and a span or two),
+// so the lattice gathers of a wave hit few cache lines.  Each lane's own
+// positions and outputs are contiguous along its ray, so the partially
+// written lines of one step are completed by the next steps.
+constexpr int kRayTile = 8;
+constexpr int kRayChunk = 64;
+
+template <int DT>
+__global__ __launch_bounds__(256) void query_rays_kernel(QueryLaunch a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tw = (a.rw + kRayTile - 1) / kRayTile, th = (a.rh + kRayTile - 1) / kRayTile;
+    const int nkc = (a.rk + kRayChunk - 1) / kRayChunk;
+    const int64_t tasks = (int64_t)tw * th * nkc;
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int wg = xcd_order(blockIdx.x, gridDim.x);
+    for (int64_t t = (int64_t)wg * (blockDim.x >> 6) + wave; t < tasks; t += wstride) {
+        const int kc = (int)(t % nkc);
+        const int64_t tile = t / nkc;
+        const int px = (int)(tile % tw) * kRayTile + (lane & (kRayTile - 1));
+        const int py = (int)(tile / tw) * kRayTile + (lane >> 3);
+        const bool ray_ok = px < a.rw && py < a.rh;
+        const int64_t ray = ray_ok ? (int64_t)py * a.rw + px : 0;
+        const int k0 = kc * kRayChunk;
+        const int k1 = min(k0 + kRayChunk, a.rk);
+        for (int k = k0; k < k1; ++k) query_sample<DT>(a, ray * a.rk + k, ray_ok);
     }
 }
 
@@ -120,10 +240,22 @@ __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
 
 hipError_t launch_query(const QueryLaunch &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    int64_t waves = (a.n + 255) / 256;
     const int64_t cap = 256 * 64;  // grid-stride beyond 64 workgroups per CU
-    const int grid = (int)(waves < cap ? waves : cap);
-    hipLaunchKernelGGL(query_kernel, dim3(grid), dim3(256), 0, s, a);
+    if (a.rk > 0) {
+        const int64_t tasks = (int64_t)((a.rw + 7) / 8) * ((a.rh + 7) / 8) *
+                              ((a.rk + kRayChunk - 1) / kRayChunk);
+        const int64_t wgs = (tasks + 3) / 4;
+        const int grid = (int)(wgs < cap ? wgs : cap);
+        if (a.dtype == FA_BF16) hipLaunchKernelGGL(query_rays_kernel<FA_BF16>, dim3(grid), dim3(256), 0, s, a);
+        else if (a.dtype == FA_F16) hipLaunchKernelGGL(query_rays_kernel<FA_F16>, dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(query_rays_kernel<FA_F32>, dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    const int64_t wgs = (a.n + 255) / 256;
+    const int grid = (int)(wgs < cap ? wgs : cap);
+    if (a.dtype == FA_BF16) hipLaunchKernelGGL(query_kernel<FA_BF16>, dim3(grid), dim3(256), 0, s, a);
+    else if (a.dtype == FA_F16) hipLaunchKernelGGL(query_kernel<FA_F16>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(query_kernel<FA_F32>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

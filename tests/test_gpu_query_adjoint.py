@@ -61,6 +61,24 @@ def test_query_c3_blocks_rays(fa):
     assert np.all(np.abs(q - r).max(0) <= 1e-5 * scale)
 
 
+@pytest.mark.parametrize("w,h,k", [(160, 90, 512), (37, 11, 70), (8, 8, 64), (3, 1, 5)])
+def test_query_rays_matches_flat(fa, w, h, k):
+    """The ray-structured order computes exactly the flat query's values
+    (ragged tiles and sample chunks included), and both match the oracle."""
+    say("query rays", w, h, k)
+    b = fi.config_c3_blocks()
+    m = models(b)
+    xyz = torch.as_tensor(fi.ray_samples_np(3, w, h, k)).cuda().contiguous()
+    boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
+    flat = fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc)
+    rays = fa.query_rays(m, xyz, w, h, k, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc)
+    assert torch.equal(flat, rays)
+    if w * h * k <= 200000:
+        r, S = oracle.query_points(oracle_blocks(b), xyz.cpu().numpy(), (16, 16, 16), (0, 0, 0),
+                                   (1, 1, 1), fi.identity_cells(4096), with_abs=True)
+        check_elementwise_bound(rays.cpu().numpy(), r, S, 64.0, "rays")
+
+
 def test_query_c3_full_sampled(fa):
     """C3 at full size: 1920x1080 rays x 512 samples generated on the GPU
     (1.06e9 samples); 300k sampled outputs checked against the oracle."""
@@ -83,7 +101,7 @@ def test_query_c3_full_sampled(fa):
         xyz[r0:r1] = (O[r0:r1, None] + D[r0:r1, None] * t[..., None]).float()
     xyz = xyz.reshape(-1, 3)
     boc = torch.as_tensor(fi.identity_cells(4096), device=dev)
-    out = fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc)
+    out = fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc)
     torch.cuda.synchronize()
     g = fi.rng(33)
     idx = torch.as_tensor(g.integers(0, xyz.shape[0], 300000), device=dev)
