@@ -283,14 +283,19 @@ def bench_c3(args):
     n = xyz.shape[0]
     boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
     out = torch.empty((n, 4), device="cuda")
-    if args.ray_order:
-        run = lambda: fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0),
-                                    (1, 1, 1), boc, out=out)
-    else:
-        run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
-    graph, _ = fa.capture(run)
-    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup,
-                               torch.cuda.current_stream())
+    flat = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
+    rays = lambda: fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                                 boc, out=out)
+    stream = torch.cuda.current_stream()
+    orders = {}
+    for name, fn in (("flat", flat), ("rays", rays)):
+        graph, _ = fa.capture(fn)
+        orders[name] = timed_steps(graph.replay, args.steps, args.warmup, stream)
+        del graph
+    best = min(orders, key=lambda k: orders[k][1])
+    ms, ev_ms, _ = orders[best]
+    (flat if best == "flat" else rays)()
+    torch.cuda.synchronize()
     g = np.random.Generator(np.random.PCG64(8))
     idx = torch.as_tensor(g.integers(0, n, 200000), device="cuda")
     xs = xyz[idx].cpu().numpy()
@@ -307,6 +312,9 @@ def bench_c3(args):
                    "block lookup + span search + value + gradient, FP32",
                    {"roofline": _roof(n * 28 + 4 * b.ctrl.size, ev_ms, "query", "c3"),
                     "valu_tflops": n * flops / (ev_ms * 1e-3) / 1e12,
+                    "order": {k: {"ms_per_step": v[0], "avg_launch_ms": v[1]}
+                              for k, v in orders.items()},
+                    "timed_order": best,
                     "err_vs_fp64": err})
     if not args.no_cpu_baseline:
         th = oracle.nthreads_default()
@@ -314,9 +322,12 @@ def bench_c3(args):
         oracle.query_points(ob, xs[:20000], (16, 16, 16), (0, 0, 0), (1, 1, 1),
                             fi.identity_cells(4096), nthreads=th)
         rate = 20000 / (time.perf_counter() - t0)
-        k = int(min(len(xs), max(20000, rate * args.cpu_seconds)))
+        k = int(min(2e7, max(20000, rate * args.cpu_seconds)))
+        idx2 = torch.as_tensor(g.integers(0, n, k), device="cuda")
+        xk = xyz[idx2].cpu().numpy()
+        del idx2
         t0 = time.perf_counter()
-        oracle.query_points(ob, xs[:k], (16, 16, 16), (0, 0, 0), (1, 1, 1),
+        oracle.query_points(ob, xk, (16, 16, 16), (0, 0, 0), (1, 1, 1),
                             fi.identity_cells(4096), nthreads=th)
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": k / dt, "unit": "samples/s", "cores": th,
@@ -469,8 +480,6 @@ def main():
     ap.add_argument("--tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
                     help="fixed decode schedule instead of the autotuner's")
-    ap.add_argument("--ray-order", action="store_true",
-                    help="C3: time fa_query_rays (8x8 ray tiles) instead of the flat order")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -203,8 +203,9 @@ fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
  * [height][width][samples][3] (ray-major, row-major pixels), out =
  * [height][width][samples][4].  Results are identical to fa_query_points
  * on the flattened arrays; only the order in which the GPU visits the
- * samples differs (a wave takes an 8 x 8 tile of rays at the same sample
- * index, where the lanes share micro-models and knot spans).
+ * samples differs (a workgroup walks a 2 x 2 tile of adjacent rays in
+ * lockstep, one ray per wave, so its waves share micro-models and knot
+ * spans at every step).
  * Errors: FA_ERR_INVALID_ARG for width, height or samples <= 0, and as
  * fa_query_points.
  */
@@ -222,7 +223,8 @@ fa_status fa_query_rays(const fa_block *blocks, int32_t nblocks, const int32_t *
  *   grad_ctrl  device FP32 lattice layout (same offsets as ctrl); the
  *              lattices of the blocks are overwritten, other elements are
  *              left untouched
- *   rows_per_item  x control planes owned per workgroup (0 = default)
+ *   rows_per_item  reserved (pass 0); one workgroup streams each block
+ * Requires res[1] <= 64 and res[2] <= 64 (FA_ERR_UNSUPPORTED otherwise).
  */
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
                              const int32_t res[3], uint32_t mask, const float *grad_out,

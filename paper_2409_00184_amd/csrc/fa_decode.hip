@@ -117,10 +117,14 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     basis_ders<P>(tz, sz, zw, zB, zD);
     const int kz0 = sz - P;
 
+    // e / plane as a multiply-shift: exact for e < 2^16 and plane < 2^14
+    // (the slab holds at most kSlabMax < 2^16 floats and plane <= 64*64)
+    const uint64_t recip = ((1ull << 30) + plane - 1) / plane;
     auto stage = [&](int c0, int c1) {
         const int cnt = (c1 - c0) * plane;
+#pragma unroll 4
         for (int e = tid; e < cnt; e += nthr) {
-            const int ii = e / plane;
+            const int ii = (int)(((uint64_t)(uint32_t)e * recip) >> 30);
             const int r = e - ii * plane;
             const int64_t gi = coff + (int64_t)((c0 + ii) * ny + jlo) * nz + r;
             sm.slab[e] = load_ctrl(a.ctrl, a.dtype, gi, scale);
@@ -346,14 +350,21 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(const fa_block *block
 template <bool NT>
 hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
     const size_t lds = sep_lds_bytes(a.rx, a.slab);
-    if (lds > 65536) {
-        const void *k = waves == 2 ? reinterpret_cast<const void *>(&decode_sep_kernel<2, NT>)
-                      : waves == 4 ? reinterpret_cast<const void *>(&decode_sep_kernel<4, NT>)
-                      : waves == 8 ? reinterpret_cast<const void *>(&decode_sep_kernel<8, NT>)
-                                   : reinterpret_cast<const void *>(&decode_sep_kernel<1, NT>);
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    // raise the dynamic LDS limit once per process to the largest layout
+    static const hipError_t attr = [] {
+        const int most = (int)sep_lds_bytes(kMaxRes, kSlabMax);
+        hipError_t r = hipSuccess, e;
+        const void *ks[4] = {reinterpret_cast<const void *>(&decode_sep_kernel<1, NT>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<2, NT>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<4, NT>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<8, NT>)};
+        for (const void *k : ks)
+            if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, most)) !=
+                hipSuccess)
+                r = e;
+        return r;
+    }();
+    if (attr != hipSuccess) return attr;
     switch (waves) {
     case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT>), dim3(grid), dim3(128), lds, s, a); break;
     case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT>), dim3(grid), dim3(256), lds, s, a); break;

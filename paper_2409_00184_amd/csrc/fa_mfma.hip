@@ -45,15 +45,17 @@ constexpr int kPtStride = 40;  // halfs per (j,k) row of the transposed slab
 constexpr int kR2Stride = 40;  // halfs per (u,v) row of R2
 constexpr int kStageStride = 68;  // floats per staged output row (64 + 4: no bank conflicts)
 
+// FP32 -> BF16 / FP16 bits, round to nearest even (the hardware conversions
+// v_cvt_pk_bf16_f32 / v_cvt_f16_f32).
 __device__ __forceinline__ uint16_t to_bits(float x, bool bf) {
-    if (bf) {
-        uint32_t u = __float_as_uint(x);
-        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite input)
-        return uint16_t(u >> 16);
-    }
-    _Float16 h = (_Float16)x;
     uint16_t r;
-    __builtin_memcpy(&r, &h, 2);
+    if (bf) {
+        __bf16 h = (__bf16)x;
+        __builtin_memcpy(&r, &h, 2);
+    } else {
+        _Float16 h = (_Float16)x;
+        __builtin_memcpy(&r, &h, 2);
+    }
     return r;
 }
 
@@ -182,17 +184,22 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
         return;
     }
 
-    // transposed slab Pt[(j,k)][i], zero padded to 16 columns x 32 K entries
+    // transposed slab Pt[(j,k)][i], zero padded to 16 columns x 32 K entries;
+    // one column per thread (consecutive threads read consecutive z points),
+    // written to LDS 8 K entries (16 bytes) at a time
     const uint16_t *P16 = static_cast<const uint16_t *>(a.ctrl) + B.ctrl_off;
-    for (int e = tid; e < nct * 16 * kK; e += blockDim.x) {
-        const int c = e % (nct * 16);  // consecutive threads: consecutive k in memory
-        const int i = e / (nct * 16);
-        uint16_t v = 0;
-        if (c < ncols && i < nx) {
-            const int j = jlo + c / nz, k = c % nz;
-            v = P16[((int64_t)i * ny + j) * nz + k];
+    const int64_t pstride = (int64_t)ny * nz;
+    for (int c = tid; c < nct * 16; c += blockDim.x) {
+        const bool cv = c < ncols;
+        const int jj = cv ? c / nz : 0;
+        const uint16_t *src = P16 + (int64_t)(jlo + jj) * nz + (c - jj * nz);
+#pragma unroll
+        for (int i8 = 0; i8 < kK; i8 += 8) {
+            u16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (cv && i8 + e < nx) ? src[(i8 + e) * pstride] : 0;
+            *reinterpret_cast<u16x8 *>(Pt + c * kPtStride + i8) = v;
         }
-        Pt[c * kPtStride + i] = v;
     }
     // R2 K padding (k >= nz) stays zero for the whole item
     for (int e = tid; e < kUC * kRows * 3 * (kK - nz); e += blockDim.x) {
@@ -264,8 +271,9 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
         }
         __syncthreads();
         // y stage: (u, k) pairs over the workgroup, all rows, three channels
-        for (int e = tid; e < kUC * nz; e += blockDim.x) {
-            const int ul = e / nz, k = e % nz;
+        for (int e = tid; e < kUC * kK; e += blockDim.x) {
+            const int ul = e >> 5, k = e & (kK - 1);
+            if (k >= nz) continue;
             const float *rb = R1B + ul * r1s + k;
             const float *rd = R1D + ul * r1s + k;
 #pragma unroll
@@ -313,13 +321,14 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                float *oc = ob + choff[ch];
-#pragma unroll 4
+                const int ub = u0 + 4 * wave;
+                float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz + w;
+                const bool wok = w < a.rz;
+#pragma unroll
                 for (int rr = 0; rr < 16; ++rr) {
-                    const int u = u0 + 4 * wave + (rr >> 2), v = row0 + (rr & 3);
                     const float val = stage[rr * kStageStride + lane];
-                    if (u < a.rx && (rr & 3) < nrows && w < a.rz)
-                        oc[(int64_t)u * plane + (int64_t)v * a.rz + w] = val;
+                    if (wok && ub + (rr >> 2) < a.rx && (rr & 3) < nrows)
+                        oc[(rr >> 2) * plane + (rr & 3) * a.rz] = val;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -381,11 +390,11 @@ hipError_t launch_decode_mfma(const DecodeLaunch &d, int waves, int grid, hipStr
         return hipErrorNotSupported;
     MfmaArgs A{d, mfma_ncmax(d.ry)};
     const size_t lds = mfma_lds_bytes(A.ncmax);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&decode_mfma_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    // raise the dynamic LDS limit once per process to the largest tile
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&decode_mfma_kernel),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mfma_lds_bytes(mfma_ncmax(2)));
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(decode_mfma_kernel, dim3(grid), dim3(256), lds, s, A);
     return hipGetLastError();
 }

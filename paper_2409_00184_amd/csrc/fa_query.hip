@@ -159,10 +159,12 @@ template <int DT>
 __device__ __forceinline__ void query_sample(const QueryLaunch &a, int64_t q, bool live) {
     float x = 0.0f, y = 0.0f, z = 0.0f;
     if (live) {
-        const Vec<3> p3 = ldv<3>(a.xyz + 3 * q);
-        x = p3.v[0];
-        y = p3.v[1];
-        z = p3.v[2];
+        // streamed once: non-temporal, so positions do not displace the
+        // lattice lines neighbouring samples and rays reuse from L2
+        const float *pp = a.xyz + 3 * q;
+        x = __builtin_nontemporal_load(pp);
+        y = __builtin_nontemporal_load(pp + 1);
+        z = __builtin_nontemporal_load(pp + 2);
     }
     float uu[3];
     const int bx = lookup_axis(x, a.origin[0], a.rscale[0], a.nb[0], uu[0]);
@@ -206,33 +208,29 @@ __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
         query_sample<DT>(a, q, q < a.n);
 }
 
-// Ray-structured: a wave owns an 8 x 8 tile of rays and walks a chunk of
-// kRayChunk sample indices; at one sample index the 64 lanes sit within a
-// pixel footprint of each other (usually one micro-model and a span or two),
-// so the lattice gathers of a wave hit few cache lines.  Each lane's own
-// positions and outputs are contiguous along its ray, so the partially
-// written lines of one step are completed by the next steps.
-constexpr int kRayTile = 8;
-constexpr int kRayChunk = 64;
+// Ray-structured: a workgroup of four waves owns a 2 x 2 tile of adjacent
+// rays; wave q walks ray q of the tile, 64 consecutive samples per step
+// (coalesced positions and outputs), and the four waves advance in lockstep
+// so that, at each step, they gather from the same micro-models and knot
+// spans and reuse each other's lattice lines in the CU's L1.
+constexpr int kRayTile = 2;
 
 template <int DT>
 __global__ __launch_bounds__(256) void query_rays_kernel(QueryLaunch a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tw = (a.rw + kRayTile - 1) / kRayTile, th = (a.rh + kRayTile - 1) / kRayTile;
-    const int nkc = (a.rk + kRayChunk - 1) / kRayChunk;
-    const int64_t tasks = (int64_t)tw * th * nkc;
-    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t tiles = (int64_t)tw * th;
     const int wg = xcd_order(blockIdx.x, gridDim.x);
-    for (int64_t t = (int64_t)wg * (blockDim.x >> 6) + wave; t < tasks; t += wstride) {
-        const int kc = (int)(t % nkc);
-        const int64_t tile = t / nkc;
-        const int px = (int)(tile % tw) * kRayTile + (lane & (kRayTile - 1));
-        const int py = (int)(tile / tw) * kRayTile + (lane >> 3);
+    for (int64_t t = wg; t < tiles; t += gridDim.x) {
+        const int px = (int)(t % tw) * kRayTile + (wave & 1);
+        const int py = (int)(t / tw) * kRayTile + (wave >> 1);
         const bool ray_ok = px < a.rw && py < a.rh;
         const int64_t ray = ray_ok ? (int64_t)py * a.rw + px : 0;
-        const int k0 = kc * kRayChunk;
-        const int k1 = min(k0 + kRayChunk, a.rk);
-        for (int k = k0; k < k1; ++k) query_sample<DT>(a, ray * a.rk + k, ray_ok);
+        for (int k0 = 0; k0 < a.rk; k0 += kWave) {
+            const int k = k0 + lane;
+            query_sample<DT>(a, ray * a.rk + k, ray_ok && k < a.rk);
+            __syncthreads();  // keep the four rays of the tile at the same depth
+        }
     }
 }
 
@@ -242,9 +240,8 @@ hipError_t launch_query(const QueryLaunch &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     const int64_t cap = 256 * 64;  // grid-stride beyond 64 workgroups per CU
     if (a.rk > 0) {
-        const int64_t tasks = (int64_t)((a.rw + 7) / 8) * ((a.rh + 7) / 8) *
-                              ((a.rk + kRayChunk - 1) / kRayChunk);
-        const int64_t wgs = (tasks + 3) / 4;
+        const int64_t wgs = (int64_t)((a.rw + kRayTile - 1) / kRayTile) *
+                            ((a.rh + kRayTile - 1) / kRayTile);
         const int grid = (int)(wgs < cap ? wgs : cap);
         if (a.dtype == FA_BF16) hipLaunchKernelGGL(query_rays_kernel<FA_BF16>, dim3(grid), dim3(256), 0, s, a);
         else if (a.dtype == FA_F16) hipLaunchKernelGGL(query_rays_kernel<FA_F16>, dim3(grid), dim3(256), 0, s, a);

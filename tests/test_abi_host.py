@@ -169,6 +169,10 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     assert L.fa_decode_blocks(vp, 1, vp, vp, 0, r, 15, None, vp, None, 0, vp, None) == 1
     assert L.fa_query_points(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
                              fa._f32x3((1, 0, 1)), vp, vp, 0, vp, 5, 15, vp, None) == 1
+    assert L.fa_query_rays(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
+                           fa._f32x3((1, 1, 1)), vp, vp, 0, vp, 0, 4, 4, 15, vp, None) == 1
+    assert L.fa_query_rays(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
+                           fa._f32x3((1, 1, 1)), vp, vp, 0, vp, 4, 4, 4, 0, vp, None) == 1
     assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, 0, None) == 2
     assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
