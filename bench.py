@@ -29,11 +29,14 @@ METRIC = "decoded voxels/sec (value+grad), batched vs plain, % HBM/MFMA roofline
 KERNEL_SOURCES = {
     "decode_sep": ["paper_2409_00184_amd/csrc/fa_decode.hip",
                    "paper_2409_00184_amd/csrc/fa_device.hpp"],
-    "query": ["paper_2409_00184_amd/csrc/fa_query.hip", "paper_2409_00184_amd/csrc/fa_device.hpp"],
+    "query": ["paper_2409_00184_amd/csrc/fa_query.hip", "paper_2409_00184_amd/csrc/fa_eval.hpp",
+              "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "decode_mfma": ["paper_2409_00184_amd/csrc/fa_mfma.hip",
                     "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "adjoint": ["paper_2409_00184_amd/csrc/fa_adjoint.hip",
                 "paper_2409_00184_amd/csrc/fa_device.hpp"],
+    "render": ["paper_2409_00184_amd/csrc/fa_render.hip", "paper_2409_00184_amd/csrc/fa_eval.hpp",
+               "paper_2409_00184_amd/csrc/fa_device.hpp"],
 }
 
 
@@ -337,6 +340,89 @@ def bench_c3(args):
     return line
 
 
+# ------------------------------------------------------------------ F1
+
+VALU_PEAK_TFLOPS = 157.3
+
+
+def bench_f1(args):
+    """Direct volume rendering of the C3 micro-models: 1920x1080 rays of the
+    seeded camera, 512 samples each (early termination off, so every sample
+    is evaluated; the terminating variant is reported beside it)."""
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import oracle
+    import paper_2409_00184_amd as fa
+    W, H, S = 1920, 1080, 512
+    b = fi.config_c3_blocks()
+    m = fa.MicroModels.from_batch(b)
+    rays_np = fi.render_rays(3, W, H)
+    rays = torch.as_tensor(rays_np, device="cuda")
+    tf_np = fi.transfer_function(4)
+    tf = torch.as_tensor(tf_np, device="cuda")
+    boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
+    img = torch.empty((H, W, 4), device="cuda")
+    shade = dict(light=(0.0, 0.6, 0.8), ka=0.3, kd=0.6, ks=0.3, shininess=16.0)
+    run = lambda omax: (lambda: fa.render(m, rays, W, H, tf, (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                                          boc, S, opacity_max=omax, tf_range=(-4.0, 4.0),
+                                          out=img, **shade))
+    stream = torch.cuda.current_stream()
+    graph, _ = fa.capture(run(0.98))
+    ms_t, ev_t, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph
+    graph, _ = fa.capture(run(2.0))
+    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph
+    run(2.0)()
+    torch.cuda.synchronize()
+    n = W * H * S
+    g = np.random.Generator(np.random.PCG64(11))
+    pix = g.integers(0, W * H, 2000)
+    got = img.reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].double().cpu().numpy()
+    ob = oracle.Blocks(b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, b.ctrl)
+    oargs = lambda r: (ob, r, S, 2.0, -4.0, 4.0, tf_np, shade["light"], shade["ka"], shade["kd"],
+                       shade["ks"], shade["shininess"], (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                       fi.identity_cells(4096))
+    ref = oracle.render(*oargs(rays_np[pix]))
+    scale = np.abs(ref).max(0)
+    err = {k: float(np.abs(got[:, c] - ref[:, c]).max() / scale[c])
+           for c, k in enumerate(["R", "G", "B", "A"])}
+    flops = 2 * 192 + 3 * 45 + 40  # contraction + basis/span + TF/shading/compositing
+    tflops = n * flops / (ev_ms * 1e-3) / 1e12
+    line = _common(args, "rendered samples/sec (DVR ray casting)", n / (ms * 1e-3), "samples/s",
+                   ms, "f32",
+                   "F1 direct volume rendering of the C3 micro-models (16^3 blocks, NCP* per "
+                   "axis in 8..32, cubic): 1920x1080 rays x 512 samples, value + gradient, "
+                   "RGBA transfer function, Blinn-Phong shading, front-to-back compositing, "
+                   "FP32; early termination off",
+                   {"roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
+                                 "traffic": traffic_from_profiles("render", "f1"),
+                                 "kernel": "render", "flops_per_sample": flops,
+                                 "avg_launch_ms": ev_ms},
+                    "frames_per_s": 1e3 / ms,
+                    "early_termination": {"opacity_max": 0.98, "ms_per_step": ms_t,
+                                          "avg_launch_ms": ev_t, "frames_per_s": 1e3 / ms_t},
+                    "err_vs_fp64": err})
+    if not args.no_cpu_baseline:
+        th = oracle.nthreads_default()
+        t0 = time.perf_counter()
+        oracle.render(*oargs(rays_np[pix[:200]]), nthreads=th)
+        rate = 200 / (time.perf_counter() - t0)
+        k = int(min(W * H, max(200, rate * args.cpu_seconds)))
+        sel = g.integers(0, W * H, k)
+        t0 = time.perf_counter()
+        oracle.render(*oargs(rays_np[sel]), nthreads=th)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": k * S / dt, "unit": "samples/s", "cores": th,
+                                "kind": "oracle",
+                                "sample": f"{k} seeded pixels of 1920x1080, {S} samples each, "
+                                          f"no early termination, FP64, {dt:.1f} s"}
+    return line
+
+
 # ------------------------------------------------------------------ C4
 
 def bench_c4(args):
@@ -438,7 +524,8 @@ def probe(args):
         xyz = c3_samples()
         boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
         out = torch.empty((xyz.shape[0], 4), device="cuda")
-        run = lambda: fa.query(m, xyz, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, out=out)
+        run = lambda: fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0),
+                                    (1, 1, 1), boc, out=out)
     elif w == "c4":
         b, _ = fi.config_c4()
         m = fa.MicroModels.from_batch(b)
@@ -475,7 +562,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1"])
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
@@ -503,7 +590,7 @@ def main():
         probe(args)
         return
     line = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-            "c5": bench_c5}[args.workload](args)
+            "c5": bench_c5, "f1": bench_f1}[args.workload](args)
     print(json.dumps(line), flush=True)
 
 

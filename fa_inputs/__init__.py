@@ -259,6 +259,34 @@ def camera_rays(seed, width, height, fov_v_deg=13.9, dist=2.0):
     return o, d, tmin, tmax, jit
 
 
+def render_rays(seed, width, height, fov_v_deg=13.9, dist=2.0):
+    """Image rays of camera_rays as FP32 [width*height, 8] = (origin, unit
+    direction, t_in, t_out); with a wide field of view some rays miss the
+    cube and get t_out <= t_in."""
+    o, d, t0, t1, _ = camera_rays(seed, width, height, fov_v_deg, dist)
+    miss = ~(t1 > t0)
+    t0 = np.where(miss, 0.0, t0)
+    t1 = np.where(miss, -1.0, t1)
+    return np.concatenate([o, d, t0[:, None], t1[:, None]], axis=1).astype(np.float32)
+
+
+def transfer_function(seed, n=256, bumps=5, alpha_max=0.08):
+    """Seeded RGBA transfer function table [n, 4] float32: colours in [0, 1]
+    from a few Gaussian bumps per channel, opacity per sample in
+    [0, alpha_max] with a transparent band around the middle of the range."""
+    g = rng(seed)
+    x = np.linspace(0.0, 1.0, n)
+    tf = np.zeros((n, 4))
+    for c in range(4):
+        mu = g.uniform(0.0, 1.0, size=bumps)
+        sd = g.uniform(0.04, 0.2, size=bumps)
+        h = g.uniform(0.2, 1.0, size=bumps)
+        f = (h[None, :] * np.exp(-0.5 * ((x[:, None] - mu[None, :]) / sd[None, :]) ** 2)).sum(1)
+        tf[:, c] = f / f.max()
+    tf[:, 3] *= alpha_max * (np.abs(x - 0.5) > 0.08)
+    return tf.astype(np.float32)
+
+
 def ray_samples_np(seed, width, height, nsamples):
     """Ray-major FP32 sample positions [width*height*nsamples, 3] (numpy).
     Sample s of a ray sits at t_in + (s + j)/nsamples * (t_out - t_in)."""

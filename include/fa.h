@@ -203,7 +203,7 @@ fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
  * [height][width][samples][3] (ray-major, row-major pixels), out =
  * [height][width][samples][4].  Results are identical to fa_query_points
  * on the flattened arrays; only the order in which the GPU visits the
- * samples differs (a workgroup walks a 2 x 2 tile of adjacent rays in
+ * samples differs (a workgroup walks a 2 x 4 tile of adjacent rays in
  * lockstep, one ray per wave, so its waves share micro-models and knot
  * spans at every step).
  * Errors: FA_ERR_INVALID_ARG for width, height or samples <= 0, and as
@@ -214,6 +214,54 @@ fa_status fa_query_rays(const fa_block *blocks, int32_t nblocks, const int32_t *
                         const float *knots, const void *ctrl, fa_dtype dtype, const float *xyz,
                         int32_t width, int32_t height, int32_t samples, uint32_t mask,
                         float *out, void *stream);
+
+/* One image ray: origin, unit direction, and the parameter interval
+ * [t0, t1] over which it is sampled (t1 <= t0: the ray misses). 32 bytes. */
+typedef struct fa_ray {
+    float origin[3];
+    float dir[3];
+    float t0, t1;
+} fa_ray;
+
+/* Ray-marching parameters of fa_render_rays (Alg. 4). */
+typedef struct fa_render_params {
+    int32_t samples;       /* samples per ray (>= 1)                           */
+    float opacity_max;     /* stop a ray once accumulated opacity exceeds it   */
+    float tf_lo, tf_hi;    /* value range covered by the transfer function     */
+    int32_t tf_size;       /* RGBA entries of the transfer function (>= 2)     */
+    float light[3];        /* unit direction towards the light                 */
+    float ka, kd, ks;      /* ambient, diffuse, specular coefficients          */
+    float shininess;       /* Blinn-Phong exponent                             */
+    float grad_min;        /* shade only where |gradient| > grad_min (>= 0)    */
+} fa_render_params;
+
+/*
+ * Direct volume rendering by front-to-back ray casting over the micro-models
+ * of a tiled domain (Alg. 4; Sec. 4.3.3): for every pixel, for samples
+ * s = 0..S-1 at getSampleLocation(s), valueMicroModel -> transfer function,
+ * gradientMicroModel -> shading, compositing, early termination once the
+ * accumulated opacity exceeds opacity_max.
+ *   blocks .. dtype  the micro-models, as for fa_query_points
+ *   rays     device fa_ray [height][width]
+ *   params   host; tf device FP32 [tf_size][4] (RGBA, A = opacity per sample)
+ *   image    device FP32 [height][width][4] = composited RGB, accumulated A
+ * Sample position, in FP32 with one rounding per operation:
+ *   dt = (t1 - t0) / S;  t = t0 + ((float)s + 0.5f) * dt;  x = o + t * d.
+ * Transfer function: q = clamp((v - tf_lo) / (tf_hi - tf_lo) * (n - 1), 0,
+ * n - 1), linear interpolation between entries floor(q) and floor(q) + 1.
+ * Shading (two-sided Blinn-Phong, V = -d, H = (L + V)/|L + V|, N = g/|g|):
+ *   rgb *= ka + kd |N.L| + ks |N.H|^shininess   (ka alone where |g| <=
+ *   grad_min: the normal of a flat region is undefined).
+ * Compositing: C += (1 - A) a rgb;  A += (1 - A) a.
+ * Errors: FA_ERR_INVALID_ARG for null pointers, width/height/samples <= 0,
+ * tf_size < 2, tf_hi <= tf_lo, grad_min < 0, and as fa_query_points.
+ */
+fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t *block_of_cell,
+                         const int32_t nb[3], const float origin[3], const float extent[3],
+                         const float *knots, const void *ctrl, fa_dtype dtype,
+                         const fa_ray *rays, int32_t width, int32_t height,
+                         const fa_render_params *params, const float *tf, float *image,
+                         void *stream);
 
 /*
  * Adjoint of the grid decode (row a7): grad_ctrl = B^T grad_out, where B

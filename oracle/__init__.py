@@ -61,8 +61,15 @@ def _load():
                                     ctypes.c_int]
     lib.orc_query_points.restype = None
     lib.orc_query_points.argtypes = [ctypes.c_int64, _f32p, _i32p, _f32p, _f32p, _i32p,
-                                     _i32p, _i32p, _i64p, _i64p, _f64p, _f64p, _f64p,
-                                     ctypes.c_void_p, ctypes.c_int]
+                                     ctypes.c_int32, _i32p, _i32p, _i64p, _i64p, _f64p, _f64p,
+                                     _f64p, ctypes.c_void_p, ctypes.c_int]
+    lib.orc_render.restype = None
+    lib.orc_render.argtypes = [ctypes.c_int64, _f32p, ctypes.c_int, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_int, _f32p,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, _f32p, _i32p, _f32p, _f32p, _i32p,
+                               ctypes.c_int32, _i32p, _i32p,
+                               _i64p, _i64p, _f64p, _f64p, _f64p, ctypes.c_int]
     lib.orc_decode_adjoint.restype = None
     lib.orc_decode_adjoint.argtypes = [ctypes.c_int32, _i32p, _i32p, _i64p, _i64p, _f64p,
                                        _i32p, ctypes.c_uint32, _f64p, _f64p, ctypes.c_int]
@@ -200,7 +207,7 @@ def query_points(b: Blocks, xyz, nb, origin, extent, block_of_cell, with_abs=Fal
     ab = np.empty((n, 4), np.float64) if with_abs else None
     _load().orc_query_points(n, xyz.reshape(-1), _c(nb, np.int32), _c(origin, np.float32),
                              _c(extent, np.float32), _c(block_of_cell, np.int32).reshape(-1),
-                             b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, b.ctrl,
+                             b.nblocks, b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, b.ctrl,
                              out.reshape(-1), ab.ctypes.data if with_abs else None,
                              nthreads or nthreads_default())
     return (out, ab) if with_abs else out
@@ -214,3 +221,21 @@ def decode_adjoint(b: Blocks, res, g, mask=1, nthreads=None):
                                _c(res, np.int32), int(mask), g, G,
                                nthreads or nthreads_default())
     return G
+
+
+def render(b: Blocks, rays, samples, opacity_max, tf_lo, tf_hi, tf, light, ka, kd, ks,
+           shininess, nb, origin, extent, block_of_cell, grad_min=1e-6, nthreads=None):
+    """Front-to-back ray casting (see orc_render).  rays: float32 [npix, 8]
+    (origin, dir, t0, t1); tf: float32 [n, 4]; returns float64 [npix, 4]."""
+    rays = _c(rays, np.float32).reshape(-1, 8)
+    tf = _c(tf, np.float32).reshape(-1, 4)
+    img = np.empty((rays.shape[0], 4), np.float64)
+    _load().orc_render(rays.shape[0], rays.reshape(-1), int(samples), float(opacity_max),
+                       float(tf_lo), float(tf_hi), tf.shape[0], _c(light, np.float32),
+                       float(ka), float(kd), float(ks), float(shininess), float(grad_min),
+                       tf.reshape(-1),
+                       _c(nb, np.int32), _c(origin, np.float32), _c(extent, np.float32),
+                       _c(block_of_cell, np.int32).reshape(-1), b.nblocks, b.ncp, b.deg,
+                       b.knot_off, b.ctrl_off, b.knots, b.ctrl, img.reshape(-1),
+                       nthreads or nthreads_default())
+    return img

@@ -287,9 +287,63 @@ void orc_eval_params(int64_t m, const int32_t *blk, const double *uvw,
  *   b   = min(floor(q), nb - 1)
  *   u   = q - b                          (exact)
  * The gradient is taken with respect to x: d/dx = r * d/du. */
+/* One point: FP32 lookup, FP64 evaluation, chain rule.  Returns 0 for an
+ * empty cell (outputs zero). */
+static int query_one(const float p[3], const int32_t nb[3], const float origin[3],
+                     const float r[3], const int32_t *block_of_cell, int32_t nblocks,
+                     const int32_t *ncp, const int32_t *deg, const int64_t *knot_off,
+                     const int64_t *ctrl_off, const double *knots, const double *ctrl,
+                     double o[4], double ao[4])
+{
+    int bidx[3];
+    double uvw[3];
+    for (int a = 0; a < 3; a++) {
+        float d = p[a] - origin[a];
+        float g = d * r[a];
+        float top = (float)nb[a];
+        if (!(g >= 0.0f)) g = 0.0f; /* also maps NaN to 0 */
+        if (g > top) g = top;
+        int b = (int)floorf(g);
+        if (b > nb[a] - 1) b = nb[a] - 1;
+        float u = g - (float)b;
+        bidx[a] = b;
+        uvw[a] = (double)u;
+    }
+    int cell = (bidx[0] * nb[1] + bidx[1]) * nb[2] + bidx[2];
+    int blk = block_of_cell[cell];
+    if (blk < 0 || blk >= nblocks) {
+        o[0] = o[1] = o[2] = o[3] = 0.0;
+        if (ao)
+            ao[0] = ao[1] = ao[2] = ao[3] = 0.0;
+        return 0;
+    }
+    double loc[4], aloc[4];
+    orc_eval_point(ncp + 3 * blk, deg + 3 * blk, knots + knot_off[blk], ctrl + ctrl_off[blk],
+                   uvw, loc, aloc);
+    o[0] = loc[0];
+    for (int a = 0; a < 3; a++)
+        o[1 + a] = loc[1 + a] * (double)r[a];
+    if (ao) {
+        ao[0] = aloc[0];
+        for (int a = 0; a < 3; a++)
+            ao[1 + a] = aloc[1 + a] * (double)r[a];
+    }
+    return 1;
+}
+
+/* Block lookup, taken in FP32 exactly as the query kernel takes it (an
+ * integer decided by floating point is decided in the same precision on
+ * both sides).  This translation unit is compiled without FP contraction,
+ * so every line of the lookup is one correctly rounded FP32 operation:
+ *   r   = (float)nb / extent            (host side, once per axis)
+ *   q   = (x - origin) * r, clamped to [0, nb]
+ *   b   = min(floor(q), nb - 1)
+ *   u   = q - b                          (exact)
+ * The gradient is taken with respect to x: d/dx = r * d/du.  A cell whose
+ * block index is negative (or not below nblocks) is empty. */
 void orc_query_points(int64_t n, const float *xyz /* [n][3] */,
                       const int32_t nb[3], const float origin[3],
-                      const float extent[3], const int32_t *block_of_cell,
+                      const float extent[3], const int32_t *block_of_cell, int32_t nblocks,
                       const int32_t *ncp, const int32_t *deg,
                       const int64_t *knot_off, const int64_t *ctrl_off,
                       const double *knots, const double *ctrl,
@@ -305,44 +359,100 @@ void orc_query_points(int64_t n, const float *xyz /* [n][3] */,
     (void)nthreads;
 #endif
     #pragma omp parallel for schedule(static)
-    for (int64_t q = 0; q < n; q++) {
-        int bidx[3];
-        double uvw[3];
-        for (int a = 0; a < 3; a++) {
-            float d = xyz[3 * q + a] - origin[a];
-            float g = d * r[a];
-            float top = (float)nb[a];
-            if (!(g >= 0.0f)) g = 0.0f; /* also maps NaN to 0 */
-            if (g > top) g = top;
-            int b = (int)floorf(g);
-            if (b > nb[a] - 1) b = nb[a] - 1;
-            float u = g - (float)b;
-            bidx[a] = b;
-            uvw[a] = (double)u;
-        }
-        int cell = (bidx[0] * nb[1] + bidx[1]) * nb[2] + bidx[2];
-        int blk = block_of_cell[cell];
-        double *o = out + 4 * q;
-        if (blk < 0) {
-            o[0] = o[1] = o[2] = o[3] = 0.0;
-            if (abs_out) {
-                double *ao = abs_out + 4 * q;
-                ao[0] = ao[1] = ao[2] = ao[3] = 0.0;
-            }
+    for (int64_t q = 0; q < n; q++)
+        query_one(xyz + 3 * q, nb, origin, r, block_of_cell, nblocks, ncp, deg, knot_off,
+                  ctrl_off, knots, ctrl, out + 4 * q, abs_out ? abs_out + 4 * q : NULL);
+}
+
+/* ------------------------------------------------------------------ */
+/* direct volume rendering (ray casting)                               */
+/* ------------------------------------------------------------------ */
+
+/* Front-to-back ray casting of Alg. 4 (Sec. 4.3.3), per pixel:
+ *   sample s at t = t0 + (s + 1/2) (t1 - t0) / S, positions in FP32 with one
+ *   rounding per operation (the same numbers the GPU forms);
+ *   value and gradient by query_one (FP32 lookup, FP64 evaluation);
+ *   RGBA transfer function, linear between entries over [tf_lo, tf_hi];
+ *   two-sided Blinn-Phong: rgb *= ka + kd |N.L| + ks |N.H|^shininess with
+ *   N = g/|g|, V = -d, H = (L + V)/|L + V| (ka alone where |g| <= grad_min);
+ *   C += (1 - A) a rgb, A += (1 - A) a; stop once A > opacity_max.
+ * rays: [npix][8] = origin xyz, dir xyz, t0, t1 (FP32); tf: [tf_size][4];
+ * image: [npix][4] = (C, A) in FP64. */
+void orc_render(int64_t npix, const float *rays, int samples, float opacity_max,
+                float tf_lo, float tf_hi, int tf_size, const float light[3], float ka,
+                float kd, float ks, float shininess, float grad_min, const float *tf,
+                const int32_t nb[3], const float origin[3], const float extent[3],
+                const int32_t *block_of_cell, int32_t nblocks, const int32_t *ncp,
+                const int32_t *deg, const int64_t *knot_off, const int64_t *ctrl_off,
+                const double *knots, const double *ctrl, double *image, int nthreads)
+{
+    float r[3];
+    for (int a = 0; a < 3; a++)
+        r[a] = (float)nb[a] / extent[a];
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < npix; q++) {
+        const float *ray = rays + 8 * q;
+        double C[3] = {0, 0, 0}, A = 0.0;
+        double *img = image + 4 * q;
+        if (!(ray[7] > ray[6])) {
+            img[0] = img[1] = img[2] = img[3] = 0.0;
             continue;
         }
-        double loc[4], aloc[4];
-        orc_eval_point(ncp + 3 * blk, deg + 3 * blk, knots + knot_off[blk],
-                       ctrl + ctrl_off[blk], uvw, loc, aloc);
-        o[0] = loc[0];
-        for (int a = 0; a < 3; a++)
-            o[1 + a] = loc[1 + a] * (double)r[a];
-        if (abs_out) {
-            double *ao = abs_out + 4 * q;
-            ao[0] = aloc[0];
-            for (int a = 0; a < 3; a++)
-                ao[1 + a] = aloc[1 + a] * (double)r[a];
+        float dt = (ray[7] - ray[6]) / (float)samples;
+        double H[3], hn = 0.0;
+        for (int a = 0; a < 3; a++) {
+            H[a] = (double)light[a] - (double)ray[3 + a];
+            hn += H[a] * H[a];
         }
+        hn = sqrt(hn);
+        for (int a = 0; a < 3 && hn > 0.0; a++)
+            H[a] /= hn;
+        for (int s = 0; s < samples; s++) {
+            float ts = ((float)s + 0.5f) * dt;
+            float tt = ray[6] + ts;
+            float p[3];
+            for (int a = 0; a < 3; a++) {
+                float step = tt * ray[3 + a];
+                p[a] = ray[a] + step;
+            }
+            double e[4];
+            query_one(p, nb, origin, r, block_of_cell, nblocks, ncp, deg, knot_off, ctrl_off,
+                      knots, ctrl, e, NULL);
+            double x = (e[0] - tf_lo) / ((double)tf_hi - tf_lo) * (tf_size - 1);
+            if (x < 0.0) x = 0.0;
+            if (x > tf_size - 1) x = tf_size - 1;
+            int i = (int)floor(x);
+            if (i > tf_size - 2) i = tf_size - 2;
+            double f = x - i;
+            double rgba[4];
+            for (int c = 0; c < 4; c++)
+                rgba[c] = (1.0 - f) * tf[4 * i + c] + f * tf[4 * (i + 1) + c];
+            if (!(rgba[3] > 0.0))
+                continue;
+            double gl = sqrt(e[1] * e[1] + e[2] * e[2] + e[3] * e[3]);
+            double shade = ka;
+            if (gl > grad_min) {
+                double dl = 0.0, dh = 0.0;
+                for (int a = 0; a < 3; a++) {
+                    dl += e[1 + a] / gl * light[a];
+                    dh += e[1 + a] / gl * H[a];
+                }
+                shade = ka + kd * fabs(dl) + ks * pow(fabs(dh), shininess);
+            }
+            double w = (1.0 - A) * rgba[3];
+            for (int c = 0; c < 3; c++)
+                C[c] += w * rgba[c] * shade;
+            A += w;
+            if (A > opacity_max)
+                break;
+        }
+        img[0] = C[0]; img[1] = C[1]; img[2] = C[2]; img[3] = A;
     }
 }
 

@@ -24,7 +24,8 @@ __all__ = ["FA_F32", "FA_BF16", "FA_F16", "BLOCK_DTYPE", "WORK_DTYPE", "FAError"
            "FADecode", "capture", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libfa.so")
+# FA_LIBRARY selects another build of the same library (e.g. a tuning variant)
+_LIB_PATH = os.environ.get("FA_LIBRARY") or os.path.join(_HERE, "libfa.so")
 
 FA_OK, FA_ERR_INVALID_ARG, FA_ERR_UNSUPPORTED, FA_ERR_DEVICE = 0, 1, 2, 3
 FA_F32, FA_BF16, FA_F16 = 0, 1, 2
@@ -43,6 +44,14 @@ class FATune(ctypes.Structure):
     _fields_ = [("rows_per_item", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("slab_floats", ctypes.c_int32), ("store", ctypes.c_int32)]
+
+
+class FARenderParams(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("opacity_max", ctypes.c_float),
+                ("tf_lo", ctypes.c_float), ("tf_hi", ctypes.c_float),
+                ("tf_size", ctypes.c_int32), ("light", ctypes.c_float * 3),
+                ("ka", ctypes.c_float), ("kd", ctypes.c_float), ("ks", ctypes.c_float),
+                ("shininess", ctypes.c_float), ("grad_min", ctypes.c_float)]
 
 
 class FAError(RuntimeError):
@@ -80,6 +89,9 @@ def _load():
     L.fa_query_rays.restype = ctypes.c_int
     L.fa_query_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32, i32,
                                 u32, vp, vp]
+    L.fa_render_rays.restype = ctypes.c_int
+    L.fa_render_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32,
+                                 vp, vp, vp, vp]
     L.fa_decode_backward.restype = ctypes.c_int
     L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
     L.fa_quantize_blocks.restype = ctypes.c_int
@@ -264,6 +276,30 @@ def query_rays(models, xyz, width, height, samples, nb, origin, extent, block_of
                            DTYPES[dtype], _ptr(xyz), int(width), int(height), int(samples),
                            int(mask), _ptr(out), _stream(stream))
     _check("fa_query_rays", st)
+    return out
+
+
+def render(models, rays, width, height, tf, nb, origin, extent, block_of_cell, samples,
+           opacity_max=0.98, tf_range=(0.0, 1.0), light=(0.0, 0.0, 1.0), ka=0.3, kd=0.6,
+           ks=0.3, shininess=32.0, grad_min=1e-6, dtype="f32", out=None, stream=None):
+    """Direct volume rendering (fa_render_rays): rays [height*width, 8] float32
+    (origin, direction, t0, t1), tf [n, 4] float32 RGBA -> image
+    [height, width, 4] float32 (composited RGB, accumulated opacity)."""
+    desc, ctrl = models.lattice(dtype, stream)
+    n = int(width) * int(height)
+    assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.numel() == 8 * n
+    assert tf.dtype == torch.float32 and tf.is_contiguous() and tf.shape[-1] == 4
+    if out is None:
+        out = torch.empty((int(height), int(width), 4), dtype=torch.float32,
+                          device=models.device)
+    p = FARenderParams(int(samples), float(opacity_max), float(tf_range[0]), float(tf_range[1]),
+                       int(tf.shape[0]), (ctypes.c_float * 3)(*[float(v) for v in light]),
+                       float(ka), float(kd), float(ks), float(shininess), float(grad_min))
+    st = lib.fa_render_rays(_ptr(desc), models.nblocks, _ptr(block_of_cell), _i32x3(nb),
+                            _f32x3(origin), _f32x3(extent), _ptr(models.knots), _ptr(ctrl),
+                            DTYPES[dtype], _ptr(rays), int(width), int(height),
+                            ctypes.byref(p), _ptr(tf), _ptr(out), _stream(stream))
+    _check("fa_render_rays", st)
     return out
 
 

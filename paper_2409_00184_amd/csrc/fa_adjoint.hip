@@ -6,8 +6,8 @@
 //   HB[i][v][w] = sum_u Bx[u][i] g0 + Dx[u][i] g1,  H2, H3 = sum_u Bx[u][i] g2, g3
 //   KB[i][j][w] = sum_v By[v][j] HB + Dy[v][j] H2,  K3 = sum_v By[v][j] H3
 //   G[i][j][k]  = sum_w Bz[w][k] KB + Dz[w][k] K3
-// One workgroup (8 waves) per micro-model streams its cotangent block once:
-// lanes own z columns, wave q owns y rows q, q+8, ...; walking x, every
+// One workgroup (16 waves) per micro-model streams its cotangent block once:
+// lanes own z columns, wave q owns y rows q, q+16, ...; walking x, every
 // lane keeps the p+1 newest partial x contractions of its columns in
 // registers (the transpose of the forward decode's sliding window).  When
 // control plane i leaves the window it is final: the workgroup writes
@@ -20,7 +20,7 @@
 namespace fa {
 namespace {
 
-constexpr int kAdjWaves = 8;
+constexpr int kAdjWaves = 16;
 constexpr int kAdjMaxYZ = 64;                      // res[1], res[2] limit
 constexpr int kAdjRows = kAdjMaxYZ / kAdjWaves;    // y rows per wave
 constexpr int kPlane = kAdjMaxYZ * kWave;          // one (v, w) plane
@@ -73,7 +73,7 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
         sm.jva[j] = sm.kwa[j] = 0x7fffffff;
         sm.jvb[j] = sm.kwb[j] = -1;
     }
-    __syncthreads();
+    lds_barrier();
     const float *tx = sm.kn, *ty = tx + nx + P + 1, *tz = ty + ny + P + 1;
     for (int u = tid; u < rx; u += nthr) tab_axis<P>(tx, nx, rx, u, sm.xB[u], sm.xD[u], sm.xS[u]);
     for (int v = tid; v < ry; v += nthr) {
@@ -90,7 +90,7 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
             atomicMax(&sm.kwb[sm.zS[w] - P + r], w);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     const int64_t vox = (int64_t)rx * ry * rz;
     const int64_t plane = (int64_t)ry * rz;
@@ -131,7 +131,7 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         for (int e = tid; e < ny * kWave; e += nthr) {
             const int j = e >> 6, ww = e & 63;
             float kb = 0.0f, k3 = 0.0f;
@@ -147,7 +147,7 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
             sm.K[0][e] = kb;
             if (DER) sm.K[1][e] = k3;
         }
-        __syncthreads();
+        lds_barrier();
         for (int e = tid; e < ny * nz; e += nthr) {
             const int j = e / nz, k = e - j * nz;
             float acc = 0.0f;
@@ -158,7 +158,7 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
             }
             Gb[((int64_t)i * ny + j) * nz + k] = acc;
         }
-        __syncthreads();
+        lds_barrier();
     };
     auto advance = [&]() {  // plane top-P is final; shift the windows by one
         if (top - P >= 0) emit(top - P);
@@ -178,22 +178,29 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
         ++top;
     };
 
-    for (int u = 0; u < rx; ++u) {
-        const int s = sm.xS[u];
-        while (top < s) advance();  // uniform over the workgroup
-        const float4 bx = sm.xB[u], dx = sm.xD[u];
+    // cotangent rows of x position u, loaded one step ahead of their use
+    float g0[kAdjRows], g1[kAdjRows], g2[kAdjRows], g3[kAdjRows];
+    float n0[kAdjRows], n1[kAdjRows], n2[kAdjRows], n3[kAdjRows];
+    auto fetch = [&](int u, float(&f0)[kAdjRows], float(&f1)[kAdjRows], float(&f2)[kAdjRows],
+                     float(&f3)[kAdjRows]) {
         const float *gu = gb + (int64_t)u * plane;
-        float g0[kAdjRows], g1[kAdjRows], g2[kAdjRows], g3[kAdjRows];
 #pragma unroll
         for (int m = 0; m < kAdjRows; ++m) {
             const int v = wave + kAdjWaves * m;
-            const bool ok = wok && v < ry;
+            const bool ok = u < rx && wok && v < ry;
             const float *gp = gu + (int64_t)(ok ? v : 0) * rz;
-            g0[m] = (ok && (mask & 1u)) ? gp[choff[0]] : 0.0f;
-            g1[m] = (ok && DER && (mask & 2u)) ? gp[choff[1]] : 0.0f;
-            g2[m] = (ok && DER && (mask & 4u)) ? gp[choff[2]] : 0.0f;
-            g3[m] = (ok && DER && (mask & 8u)) ? gp[choff[3]] : 0.0f;
+            f0[m] = (ok && (mask & 1u)) ? gp[choff[0]] : 0.0f;
+            f1[m] = (ok && DER && (mask & 2u)) ? gp[choff[1]] : 0.0f;
+            f2[m] = (ok && DER && (mask & 4u)) ? gp[choff[2]] : 0.0f;
+            f3[m] = (ok && DER && (mask & 8u)) ? gp[choff[3]] : 0.0f;
         }
+    };
+    fetch(0, g0, g1, g2, g3);
+    for (int u = 0; u < rx; ++u) {
+        fetch(u + 1, n0, n1, n2, n3);
+        const int s = sm.xS[u];
+        while (top < s) advance();  // uniform over the workgroup
+        const float4 bx = sm.xB[u], dx = sm.xD[u];
 #pragma unroll
         for (int m = 0; m < kAdjRows; ++m) {
 #pragma unroll
@@ -206,13 +213,20 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
                 }
             }
         }
+#pragma unroll
+        for (int m = 0; m < kAdjRows; ++m) {
+            g0[m] = n0[m];
+            g1[m] = n1[m];
+            g2[m] = n2[m];
+            g3[m] = n3[m];
+        }
     }
     // the last P+1 planes (and any never reached) are final now
     while (top < nx + P) advance();
 }
 
 template <bool DER>
-__global__ __launch_bounds__(512) void adjoint_kernel(const fa_block *blocks, int nblocks,
+__global__ __launch_bounds__(1024) void adjoint_kernel(const fa_block *blocks, int nblocks,
                                                      const float *knots, int rx, int ry, int rz,
                                                      uint32_t mask, int nch, const float *g,
                                                      float *G) {
@@ -224,7 +238,7 @@ __global__ __launch_bounds__(512) void adjoint_kernel(const fa_block *blocks, in
         if (p == 3) adj_block<3, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
         else if (p == 2) adj_block<2, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
         else adj_block<1, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
-        __syncthreads();
+        lds_barrier();
     }
 }
 

@@ -313,6 +313,41 @@ fa_status fa_query_rays(const fa_block *blocks, int32_t nblocks, const int32_t *
                         samples, stream);
 }
 
+fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t *block_of_cell,
+                         const int32_t nb[3], const float origin[3], const float extent[3],
+                         const float *knots, const void *ctrl, fa_dtype dtype,
+                         const fa_ray *rays, int32_t width, int32_t height,
+                         const fa_render_params *params, const float *tf, float *image,
+                         void *stream) {
+    if (!blocks || nblocks <= 0 || !block_of_cell || !nb || !origin || !extent || !knots ||
+        !ctrl || !rays || !params || !tf || !image || width <= 0 || height <= 0)
+        return FA_ERR_INVALID_ARG;
+    if (dtype != FA_F32 && dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
+    const fa_render_params &p = *params;
+    if (p.samples <= 0 || p.tf_size < 2 || !(p.tf_hi > p.tf_lo) || !std::isfinite(p.tf_lo) ||
+        !std::isfinite(p.tf_hi) || !(p.grad_min >= 0.0f))
+        return FA_ERR_INVALID_ARG;
+    QueryLaunch a{};
+    for (int k = 0; k < 3; ++k) {
+        if (nb[k] <= 0 || !(extent[k] > 0.0f) || !std::isfinite(origin[k]) ||
+            !std::isfinite(extent[k]))
+            return FA_ERR_INVALID_ARG;
+        a.nb[k] = nb[k];
+        a.origin[k] = origin[k];
+        a.rscale[k] = (float)nb[k] / extent[k];
+    }
+    if ((int64_t)nb[0] * nb[1] * nb[2] > (int64_t)1 << 30) return FA_ERR_UNSUPPORTED;
+    a.blocks = blocks;
+    a.nblocks = nblocks;
+    a.block_of_cell = block_of_cell;
+    a.knots = knots;
+    a.ctrl = ctrl;
+    a.dtype = dtype;
+    a.mask = 15u;
+    hipError_t e = launch_render(a, rays, width, height, p, tf, image, (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
                              const int32_t res[3], uint32_t mask, const float *grad_out,
                              float *grad_ctrl, int32_t rows_per_item, void *stream) {

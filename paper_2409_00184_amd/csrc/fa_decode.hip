@@ -83,9 +83,9 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     const float scale = B.scale;
     const int nkn = nx + ny + nz + 3 * (P + 1);
 
-    __syncthreads();  // the previous item is done with the shared buffers
+    lds_barrier();  // the previous item is done with the shared buffers
     for (int e = tid; e < nkn; e += nthr) sm.kn[e] = a.knots[koff + e];
-    __syncthreads();
+    lds_barrier();
     const float *tx = sm.kn;
     const float *ty = tx + nx + P + 1;
     const float *tz = ty + ny + P + 1;
@@ -131,10 +131,10 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         }
     };
 
-    __syncthreads();  // x table visible
+    lds_barrier();  // x table visible
     if (single) {
         stage(0, nx);
-        __syncthreads();
+        lds_barrier();
     }
 
     const int64_t vox = (int64_t)a.rx * a.ry * a.rz;
@@ -160,9 +160,9 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
 
         int clo = 0, chi = ic;
         if (!single) {
-            __syncthreads();
+            lds_barrier();
             stage(0, ic);
-            __syncthreads();
+            lds_barrier();
         }
 
         float wBB[P + 1], wDB[P + 1], wBD[P + 1];
@@ -177,11 +177,11 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
             while (top < s) {  // uniform over the workgroup
                 ++top;
                 if (top >= chi) {
-                    __syncthreads();
+                    lds_barrier();
                     clo = chi;
                     chi = min(clo + ic, nx);
                     stage(clo, chi);
-                    __syncthreads();
+                    lds_barrier();
                 }
                 const float *sl = sm.slab + (top - clo) * plane + jrow * nz + kz0;
                 float tB[P + 1], tD[P + 1];

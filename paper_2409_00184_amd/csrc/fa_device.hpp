@@ -154,6 +154,16 @@ __device__ __forceinline__ void basis_ders_rt(const float *t, int s, float u, in
     }
 }
 
+// Workgroup barrier for LDS hand-offs only: orders LDS accesses around
+// s_barrier without waiting for outstanding global loads and stores (which
+// __syncthreads() would drain), so prefetches and output stores stay in
+// flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // XCD-aware workgroup order.  The dispatcher deals workgroups round-robin
 // over the 8 XCDs (workgroup b runs on XCD b % 8), each with its own L2.
 // This maps b to a logical index so that the workgroups one XCD runs are

@@ -58,6 +58,10 @@ struct QueryLaunch {
 
 hipError_t launch_query(const QueryLaunch &a, hipStream_t s);
 
+hipError_t launch_render(const QueryLaunch &q, const fa_ray *rays, int width, int height,
+                         const fa_render_params &p, const float *tf, float *image,
+                         hipStream_t s);
+
 hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
                           int ry, int rz, uint32_t mask, const float *g, float *G, int it,
                           hipStream_t s);

@@ -166,10 +166,10 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
     float *ytab = kn + kMaxKnotsPerBlock + 4;  // per row: By[4], Dy[4], window start
     const int P = B.degree[0];
 
-    __syncthreads();  // previous item done with LDS
+    lds_barrier();  // previous item done with LDS
     const int nkn = nx + ny + nz + 3 * (P + 1);
     for (int e = tid; e < nkn; e += blockDim.x) kn[e] = a.knots[B.knot_off + e];
-    __syncthreads();
+    lds_barrier();
     const float *tx = kn, *ty = tx + nx + P + 1, *tz = ty + ny + P + 1;
 
     const int jlo = span_search(ny, P, ty, grid_pos(row0, a.ry)) - P;
@@ -245,7 +245,7 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
     }
     float *ob = a.out + (int64_t)b * a.nch * vox;
     const float scale = B.scale;
-    __syncthreads();  // slab and padding visible
+    lds_barrier();  // slab and padding visible
 
     for (int u0 = 0; u0 < a.rx; u0 += kUC) {
         // x stage: A = x basis rows u0..u0+15, B = slab columns
@@ -269,7 +269,7 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         // y stage: (u, k) pairs over the workgroup, all rows, three channels
         for (int e = tid; e < kUC * kK; e += blockDim.x) {
             const int ul = e >> 5, k = e & (kK - 1);
@@ -295,7 +295,7 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
                 R2[(2 * kUC * kRows + row) * kR2Stride + k] = to_bits(bd, bf);
             }
         }
-        __syncthreads();
+        lds_barrier();
         // z stage: wave q owns R2 rows 16q..16q+15 = x voxels u0+4q..u0+4q+3,
         // 4 rows.  Each channel's 4 x 4 x 64 tile goes through this wave's
         // LDS region (the R1 buffer, dead until the next chunk) so every
@@ -335,7 +335,7 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        __syncthreads();  // R1/R2 reused by the next chunk
+        lds_barrier();  // R1/R2 reused by the next chunk
     }
 }
 

@@ -69,3 +69,36 @@ def mixed_batch(seed, nblocks, ncp_lo=2, ncp_hi=20, degs=(1, 2, 3), nonuniform=0
         kl.append(ks)
         lat.append(g.normal(size=n))
     return fi.pack(ncp, deg, kl, lat)
+
+
+def host_quantize(b, dtype):
+    """Reference of fa_quantize_blocks: s = max|P| (1 if zero), q =
+    clamp(P * fl(1/s), -1, 1) in FP32, then RNE to the 2-byte type."""
+    codes = np.zeros(b.ctrl.size, np.uint16)
+    scales = np.zeros(b.nblocks, np.float32)
+    for k in range(b.nblocks):
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        P = b.ctrl[o:o + n].astype(np.float32)
+        s = np.float32(np.abs(P).max()) if np.abs(P).max() > 0 else np.float32(1.0)
+        inv = np.float32(1.0) / s
+        q = np.clip(P * inv, np.float32(-1), np.float32(1)).astype(np.float32)
+        if dtype == "bf16":
+            u = q.view(np.uint32).astype(np.uint64)
+            u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+            codes[o:o + n] = u.astype(np.uint16)
+        else:
+            codes[o:o + n] = q.astype(np.float16).view(np.uint16)
+        scales[k] = s
+    return codes, scales
+
+
+def dequant(b, codes, scales, dtype):
+    out = np.zeros(b.ctrl.size, np.float64)
+    if dtype == "bf16":
+        vals = (codes.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    else:
+        vals = codes.view(np.float16).astype(np.float64)
+    for k in range(b.nblocks):
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        out[o:o + n] = vals[o:o + n] * float(scales[k])
+    return out

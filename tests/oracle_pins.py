@@ -19,6 +19,7 @@ paper cites in Sec. 1 -- and the micro-model content of Sec. 4.2 / Eq. 2):
   brute       local evaluation equals the all-basis brute force
   adjoint     <B P, g> = <P, B^T g>
   query       block lookup + chain rule on a tiled domain of linear blocks
+  render      compositing, termination and shading closed forms
 """
 import math
 import os
@@ -359,5 +360,62 @@ def pin_query():
         assert np.allclose(out[q, 1:], np.array([b1, b2, b3]) * r, atol=1e-8)
 
 
+def _one_block_linear(a0, bx, by, bz, n=6, p=3):
+    t = fi.clamped_uniform_knots(n, p).astype(np.float64)
+    xi = _greville(t, n, p)
+    P = a0 + bx * xi[:, None, None] + by * xi[None, :, None] + bz * xi[None, None, :]
+    bt = fi.pack([(n, n, n)], [(p, p, p)], [[t, t, t]], [P])
+    return oracle.Blocks(bt.ncp, bt.deg, bt.knot_off, bt.ctrl_off, bt.knots, bt.ctrl)
+
+
+def pin_render():
+    """Closed forms of front-to-back compositing over one block:
+    constant field -> A = 1 - (1 - a)^S and C = rgb * ka * A (gradient 0);
+    early termination stops at the first S' with 1 - (1 - a)^S' > O_max;
+    linear field of gradient g -> every sample shaded by
+    ka + kd |n.L| + ks |n.H|^m with n = g/|g|."""
+    nb, origin, extent = (1, 1, 1), (0, 0, 0), (1, 1, 1)
+    boc = np.zeros(1, np.int32)
+    rays = np.array([[0.1, 0.5, 0.5, 1, 0, 0, 0.0, 0.8],
+                     [0.5, 0.2, 0.3, 0, 0.8, 0.6, 0.0, 0.5],
+                     [0.5, 0.5, 0.5, 1, 0, 0, 0.4, 0.1]], np.float32)  # last one misses
+    light = np.array([0.0, 0.6, 0.8], np.float32)
+    alpha, rgb = float(np.float32(0.05)), (0.9, 0.5, 0.2)  # the TF holds FP32 values
+    tf = np.array([[*rgb, alpha], [*rgb, alpha]], np.float32)
+    # constant field (a linear field with zero slope)
+    blk = _one_block_linear(0.3, 0.0, 0.0, 0.0)
+    S = 37
+    img = oracle.render(blk, rays, S, 2.0, -1.0, 1.0, tf, light, 0.4, 0.5, 0.3, 16.0, nb,
+                        origin, extent, boc)
+    A = 1 - (1 - alpha) ** S
+    for q in range(2):
+        assert abs(img[q, 3] - A) < 1e-12
+        assert np.allclose(img[q, :3], np.array(rgb, np.float64).astype(np.float32) * 0.4 * A,
+                           atol=1e-7)
+    assert np.all(img[2] == 0.0)
+    # early termination
+    omax = 0.5
+    img = oracle.render(blk, rays, S, omax, -1.0, 1.0, tf, light, 0.4, 0.5, 0.3, 16.0, nb,
+                        origin, extent, boc)
+    Sp = next(k for k in range(1, S + 1) if 1 - (1 - alpha) ** k > omax)
+    assert abs(img[0, 3] - (1 - (1 - alpha) ** Sp)) < 1e-12
+    # linear field: constant gradient (world units = block units here)
+    g = np.array([0.3, -1.2, 0.7])
+    blk = _one_block_linear(0.1, *g)
+    img = oracle.render(blk, rays[:2], S, 2.0, -10.0, 10.0, tf, light, 0.4, 0.5, 0.3, 16.0, nb,
+                        origin, extent, boc)
+    nrm = g / np.linalg.norm(g)
+    L = light.astype(np.float64)
+    for q in range(2):
+        d = rays[q, 3:6].astype(np.float64)
+        H = L - d
+        H /= np.linalg.norm(H)
+        shade = 0.4 + 0.5 * abs(nrm @ L) + 0.3 * abs(nrm @ H) ** 16.0
+        assert abs(img[q, 3] - A) < 1e-12
+        want = np.array(rgb, np.float32).astype(np.float64) * shade * A
+        assert np.allclose(img[q, :3], want, atol=1e-9), (img[q], want)
+
+
 ALL_PINS = [pin_span, pin_unity, pin_bernstein, pin_cardinal, pin_linear, pin_quadratic,
-            pin_corners, pin_fd, pin_brute, pin_decode_layout, pin_adjoint, pin_query]
+            pin_corners, pin_fd, pin_brute, pin_decode_layout, pin_adjoint, pin_query,
+            pin_render]

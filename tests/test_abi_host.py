@@ -3,6 +3,7 @@ its host-only calls (validation, batch plan) behave as documented (CPU)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -40,6 +41,28 @@ def test_struct_layouts(fa):
     assert fa.BLOCK_DTYPE.fields["ctrl_off"][1] == 32
     assert fa.BLOCK_DTYPE.fields["scale"][1] == 40
     assert fa.WORK_DTYPE.itemsize == 12
+
+
+def test_struct_layouts_match_header(fa, tmp_path):
+    """sizeof/offsetof as a C compiler sees include/fa.h == the binding's."""
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "fa.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+        ' sizeof(fa_block), sizeof(fa_work), sizeof(fa_tune), sizeof(fa_ray),'
+        ' sizeof(fa_render_params), offsetof(fa_render_params, light),'
+        ' offsetof(fa_render_params, grad_min), offsetof(fa_tune, store),'
+        ' offsetof(fa_block, scale)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [fa.BLOCK_DTYPE.itemsize, fa.WORK_DTYPE.itemsize, ctypes.sizeof(fa.FATune), 32,
+            ctypes.sizeof(fa.FARenderParams), fa.FARenderParams.light.offset,
+            fa.FARenderParams.grad_min.offset, fa.FATune.store.offset,
+            fa.BLOCK_DTYPE.fields["scale"][1]]
+    assert got == want
 
 
 def _desc(fa, b):
@@ -173,6 +196,22 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
                            fa._f32x3((1, 1, 1)), vp, vp, 0, vp, 0, 4, 4, 15, vp, None) == 1
     assert L.fa_query_rays(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
                            fa._f32x3((1, 1, 1)), vp, vp, 0, vp, 4, 4, 4, 0, vp, None) == 1
+    rp = fa.FARenderParams(16, 0.98, -1.0, 1.0, 2, (ctypes.c_float * 3)(0, 0, 1), 0.3, 0.6,
+                           0.3, 32.0, 1e-6)
+    args = lambda w, h, p: (vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
+                            fa._f32x3((1, 1, 1)), vp, vp, 0, vp, w, h, ctypes.byref(p), vp, vp,
+                            None)
+    for bad in (dict(samples=0), dict(tf_size=1), dict(tf_hi=-1.0), dict(grad_min=-1.0),
+                dict(tf_lo=float("nan"))):
+        q = fa.FARenderParams.from_buffer_copy(rp)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert L.fa_render_rays(*args(4, 4, q)) == 1, bad
+    assert L.fa_render_rays(*args(0, 4, rp)) == 1
+    assert L.fa_render_rays(*args(4, -1, rp)) == 1
+    a = list(args(4, 4, rp))
+    a[13] = None  # no transfer function
+    assert L.fa_render_rays(*a) == 1
     assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, 0, None) == 2
     assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1

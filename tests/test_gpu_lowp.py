@@ -15,7 +15,7 @@ import torch
 
 import fa_inputs as fi
 import oracle
-from gpu_util import U32, mixed_batch, models, oracle_blocks, say
+from gpu_util import U32, dequant, host_quantize, mixed_batch, models, oracle_blocks, say
 
 pytestmark = pytest.mark.gpu
 ULP = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
@@ -26,39 +26,6 @@ def fa():
     import paper_2409_00184_amd as fa
     assert torch.cuda.is_available()
     return fa
-
-
-def host_quantize(b, dtype):
-    """Reference of fa_quantize_blocks: s = max|P| (1 if zero), q =
-    clamp(P * fl(1/s), -1, 1) in FP32, then RNE to the 2-byte type."""
-    codes = np.zeros(b.ctrl.size, np.uint16)
-    scales = np.zeros(b.nblocks, np.float32)
-    for k in range(b.nblocks):
-        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
-        P = b.ctrl[o:o + n].astype(np.float32)
-        s = np.float32(np.abs(P).max()) if np.abs(P).max() > 0 else np.float32(1.0)
-        inv = np.float32(1.0) / s
-        q = np.clip(P * inv, np.float32(-1), np.float32(1)).astype(np.float32)
-        if dtype == "bf16":
-            u = q.view(np.uint32).astype(np.uint64)
-            u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-            codes[o:o + n] = u.astype(np.uint16)
-        else:
-            codes[o:o + n] = q.astype(np.float16).view(np.uint16)
-        scales[k] = s
-    return codes, scales
-
-
-def dequant(b, codes, scales, dtype):
-    out = np.zeros(b.ctrl.size, np.float64)
-    if dtype == "bf16":
-        vals = (codes.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-    else:
-        vals = codes.view(np.float16).astype(np.float64)
-    for k in range(b.nblocks):
-        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
-        out[o:o + n] = vals[o:o + n] * float(scales[k])
-    return out
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])

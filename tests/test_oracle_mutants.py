@@ -25,6 +25,11 @@ MUTANTS = [
      "N[0][ri] * D[1][rj] * N[2][rk] * gc[1]"),
     ("grid_position_cell_centred", "float q = (float)i / (float)(R - 1);",
      "float q = ((float)i + 0.5f) / (float)R;"),
+    ("render_back_to_front", "double w = (1.0 - A) * rgba[3];", "double w = rgba[3];"),
+    ("render_shading_ignores_half_vector", "dh += e[1 + a] / gl * H[a];",
+     "dh += e[1 + a] / gl * light[a];"),
+    ("render_no_termination", "if (A > opacity_max)\n                break;",
+     "if (A > 2.0 * opacity_max + 1.0)\n                break;"),
 ]
 
 
