@@ -289,6 +289,89 @@ fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const floa
 fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctrl_f32,
                              fa_dtype dtype, void *ctrl_lp, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Adaptive encoding (Sec. 4.2): fit, error map, NCP selection         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Least-squares fit of every micro-model's lattice to samples on its decode
+ * grid: the model(NCP, degree) step of Alg. 1 (Sec. 4.2.1).  With B the
+ * value map of fa_decode_blocks at `res` (grid u_i = fl32(i / (res - 1))),
+ * ctrl = argmin_P |y - B P|_2 = y x_1 B_x^+ x_2 B_y^+ x_3 B_z^+, computed as
+ * B^T y (the decode adjoint) followed by a band Cholesky solve with the Gram
+ * matrix B_a^T B_a along each axis (factor in FP64, lines solved in FP64,
+ * stored FP32).
+ *   blocks, knots  device descriptors/knots (FP32 lattices); ncp[a] <= res[a]
+ *                  is the caller's to guarantee (a larger ncp makes the Gram
+ *                  matrix singular and the lattice non-finite)
+ *   samples        device FP32 [nblocks][res0][res1][res2]
+ *   ctrl           device FP32, lattice layout; the blocks' lattices are
+ *                  overwritten, other elements are left untouched
+ * Errors: FA_ERR_INVALID_ARG for null pointers, nblocks <= 0, res < 2;
+ * FA_ERR_UNSUPPORTED for res[0] > FA_MAX_RES or res[1], res[2] > 64.
+ */
+fa_status fa_fit_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
+                        const int32_t res[3], const float *samples, float *ctrl, void *stream);
+
+/*
+ * Error of every micro-model against samples on its decode grid (Error(NCP)
+ * of Eq. 4): with f the value decode at `res`,
+ *   errs[b * errs_stride + 0] = max |y - f|,
+ *   errs[b * errs_stride + 1] = sqrt(mean (y - f)^2)   (FP64 sum of squares).
+ *   decoded  device FP32 [nblocks][res0][res1][res2], filled with f
+ *            (caller-owned workspace: the call allocates nothing)
+ *   errs     device FP32, errs_stride >= 2
+ * Deterministic.  Errors as fa_decode_blocks, and FA_ERR_INVALID_ARG for a
+ * null samples/decoded/errs or errs_stride < 2.
+ */
+fa_status fa_model_errors(const fa_block *blocks, int32_t nblocks, const float *knots,
+                          const void *ctrl, fa_dtype dtype, const int32_t res[3],
+                          const float *samples, float *decoded, float *errs,
+                          int64_t errs_stride, void *stream);
+
+/* Bytes of device workspace fa_ncp_search needs (-1 for invalid sizes). */
+int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t degree,
+                                int32_t ncp_hi);
+
+/*
+ * In-level exhaustive search of Sec. 4.2.1 (the inner loop of Alg. 1): for
+ * every NCP n from ncp_hi down to ncp_lo, every block is fitted with n
+ * control points per axis (clamped uniform knots t_{p+j} = j / (n - p),
+ * degree `degree` on every axis) and its error map entry is written:
+ *   errs[(b * ncand + (n - ncp_lo)) * 2 + {0, 1}] = (max, rms) as
+ *   fa_model_errors, ncand = ncp_hi - ncp_lo + 1.
+ *   samples    device FP32 [nblocks][res0][res1][res2]
+ *   workspace  device, >= fa_ncp_search_workspace(...) bytes, 256-B aligned
+ * Requires degree + 1 <= ncp_lo <= ncp_hi <= min(res) (FA_ERR_INVALID_ARG
+ * otherwise); degree > 3, ncp_hi > FA_MAX_NCP, res[1] or res[2] > 64 give
+ * FA_ERR_UNSUPPORTED.  Asynchronous on `stream`; no allocation.
+ */
+fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res[3],
+                        int32_t degree, int32_t ncp_lo, int32_t ncp_hi, float *errs,
+                        void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * NCP* of Eq. 4 from host error maps laid out as fa_ncp_search writes them:
+ * ncp_star[b] = the smallest n whose error (metric 0: max, 1: rms) is below
+ * `bound`, or the largest candidate when none is; complex_[b] (may be null)
+ * = 1 when some candidate's error exceeds `bound` (the complex-set test of
+ * Alg. 1), else 0.  Host only.
+ */
+fa_status fa_ncp_select(const float *errs, int32_t nblocks, int32_t ncand, int32_t ncp_lo,
+                        int32_t metric, float bound, int32_t *ncp_star, int32_t *complex_);
+
+/*
+ * Host layout of a batch of micro-models with clamped uniform knots: for
+ * per-block ncp[b][3] and degree[b][3] (equal on the axes), fills the
+ * descriptors (may be null), the knots (may be null; t_{p+j} = fl32(j /
+ * (n - p))) and returns the knot and lattice element counts; lattices start
+ * at multiples of 64 elements (256 B in FP32).  FA_ERR_INVALID_ARG for
+ * ncp < degree + 1, degree < 1, unequal degrees or too small a capacity.
+ */
+fa_status fa_uniform_layout(int32_t nblocks, const int32_t *ncp, const int32_t *degree,
+                            fa_block *blocks, float *knots, int64_t knot_capacity,
+                            int64_t *nknots, int64_t *nctrl);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,18 @@ def _load():
     L.fa_render_rays.restype = ctypes.c_int
     L.fa_render_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32,
                                  vp, vp, vp, vp]
+    L.fa_fit_blocks.restype = ctypes.c_int
+    L.fa_fit_blocks.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.fa_model_errors.restype = ctypes.c_int
+    L.fa_model_errors.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, vp, vp, vp, i64, vp]
+    L.fa_ncp_search_workspace.restype = i64
+    L.fa_ncp_search_workspace.argtypes = [i32, vp, i32, i32]
+    L.fa_ncp_search.restype = ctypes.c_int
+    L.fa_ncp_search.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, i64, vp]
+    L.fa_ncp_select.restype = ctypes.c_int
+    L.fa_ncp_select.argtypes = [vp, i32, i32, i32, i32, ctypes.c_float, vp, vp]
+    L.fa_uniform_layout.restype = ctypes.c_int
+    L.fa_uniform_layout.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp]
     L.fa_decode_backward.restype = ctypes.c_int
     L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
     L.fa_quantize_blocks.restype = ctypes.c_int
@@ -313,6 +325,128 @@ def decode_backward(models, res, grad_out, mask=1, grad_ctrl=None, rows=0, strea
                                 int(rows), _stream(stream))
     _check("fa_decode_backward", st)
     return grad_ctrl
+
+
+# ------------------------------------------------------- adaptive encoding
+
+def uniform_models(ncp, degree, device="cuda"):
+    """MicroModels with clamped uniform knots for per-block ncp [nb, 3] and
+    degree [nb] or [nb, 3] (fa_uniform_layout); lattices zero."""
+    ncp = np.ascontiguousarray(np.asarray(ncp, np.int32).reshape(-1, 3))
+    nb = ncp.shape[0]
+    deg = np.asarray(degree, np.int32)
+    deg = np.ascontiguousarray(np.broadcast_to(deg.reshape(-1, 1) if deg.ndim == 1 else deg,
+                                               (nb, 3)), np.int32)
+    desc = np.zeros(nb, BLOCK_DTYPE)
+    nk, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check("fa_uniform_layout", lib.fa_uniform_layout(nb, ncp.ctypes.data, deg.ctypes.data,
+                                                      None, None, 0, ctypes.byref(nk),
+                                                      ctypes.byref(nc)))
+    knots = np.zeros(nk.value, np.float32)
+    _check("fa_uniform_layout", lib.fa_uniform_layout(nb, ncp.ctypes.data, deg.ctypes.data,
+                                                      desc.ctypes.data, knots.ctypes.data,
+                                                      knots.size, ctypes.byref(nk),
+                                                      ctypes.byref(nc)))
+    return MicroModels(desc["ncp"], desc["degree"], desc["knot_off"], desc["ctrl_off"], knots,
+                       np.zeros(nc.value, np.float32), device)
+
+
+def fit(models, res, samples, stream=None):
+    """Least-squares lattices (fa_fit_blocks) of samples [nb, *res] float32;
+    overwrites models.ctrl (and drops low-precision copies)."""
+    assert samples.dtype == torch.float32 and samples.is_contiguous()
+    assert samples.numel() == models.nblocks * int(np.prod(res))
+    st = lib.fa_fit_blocks(_ptr(models.desc), models.nblocks, _ptr(models.knots), _i32x3(res),
+                           _ptr(samples), _ptr(models.ctrl), _stream(stream))
+    _check("fa_fit_blocks", st)
+    models.set_ctrl(models.ctrl)
+    return models
+
+
+def model_errors(models, res, samples, dtype="f32", decoded=None, stream=None):
+    """Per-block (max |y - f|, rms(y - f)) of the decoded models (fa_model_errors)."""
+    desc, ctrl = models.lattice(dtype, stream)
+    assert samples.dtype == torch.float32 and samples.is_contiguous()
+    if decoded is None:
+        decoded = torch.empty_like(samples)
+    errs = torch.empty((models.nblocks, 2), dtype=torch.float32, device=models.device)
+    st = lib.fa_model_errors(_ptr(desc), models.nblocks, _ptr(models.knots), _ptr(ctrl),
+                             DTYPES[dtype], _i32x3(res), _ptr(samples), _ptr(decoded),
+                             _ptr(errs), 2, _stream(stream))
+    _check("fa_model_errors", st)
+    return errs
+
+
+def ncp_search(samples, degree, ncp_lo=None, ncp_hi=None, workspace=None, stream=None):
+    """Error maps [nb, ncand, 2] (max, rms) of model(n, degree) for n =
+    ncp_lo..ncp_hi (fa_ncp_search); samples [nb, R0, R1, R2] float32."""
+    assert samples.dtype == torch.float32 and samples.is_contiguous() and samples.dim() == 4
+    nb, res = samples.shape[0], tuple(int(r) for r in samples.shape[1:])
+    lo = degree + 2 if ncp_lo is None else int(ncp_lo)
+    hi = min(res) if ncp_hi is None else int(ncp_hi)
+    need = lib.fa_ncp_search_workspace(nb, _i32x3(res), int(degree), hi)
+    if need < 0:
+        raise FAError("fa_ncp_search_workspace", FA_ERR_INVALID_ARG)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=samples.device)
+    errs = torch.empty((nb, hi - lo + 1, 2), dtype=torch.float32, device=samples.device)
+    st = lib.fa_ncp_search(_ptr(samples), nb, _i32x3(res), int(degree), lo, hi, _ptr(errs),
+                           _ptr(workspace), workspace.numel(), _stream(stream))
+    _check("fa_ncp_search", st)
+    return errs
+
+
+METRIC_MAX, METRIC_RMS = 0, 1
+
+
+def ncp_select(errs, ncp_lo, bound, metric=METRIC_RMS):
+    """(NCP* [nb], complex [nb]) of Eq. 4 from error maps (fa_ncp_select)."""
+    e = np.ascontiguousarray(errs.cpu().numpy() if torch.is_tensor(errs) else errs, np.float32)
+    nb, ncand = e.shape[0], e.shape[1]
+    nstar = np.zeros(nb, np.int32)
+    cplx = np.zeros(nb, np.int32)
+    st = lib.fa_ncp_select(e.ctypes.data, nb, ncand, int(ncp_lo), int(metric), float(bound),
+                           nstar.ctypes.data, cplx.ctypes.data)
+    _check("fa_ncp_select", st)
+    return nstar, cplx.astype(bool)
+
+
+def adaptive_encode(levels, degree, bound, metric=METRIC_RMS, ncp_lo=None, ncp_hi=None):
+    """Cross-level adaptive encoding (Alg. 1) over a pyramid of micro-blocks.
+
+    levels[k]: samples [(2^k)^3, R, R, R] float32 on the GPU, level 0 the
+    coarsest, block (bx, by, bz) of level k at (bx * 2^k + by) * 2^k + bz.
+    Level 0 is searched in full; a block of level k > 0 is searched only if
+    its parent is complex, otherwise it takes NCP* = degree + 1.  Every block
+    is then fitted at its NCP*.  Returns, per level, a dict with ncp_star,
+    complex, searched (numpy) and the fitted MicroModels."""
+    out = []
+    prev = None
+    for k, Y in enumerate(levels):
+        nb, R = Y.shape[0], int(Y.shape[1])
+        lo = degree + 2 if ncp_lo is None else int(ncp_lo)
+        hi = R if ncp_hi is None else int(ncp_hi)
+        nstar = np.full(nb, degree + 1, np.int32)
+        cplx = np.zeros(nb, bool)
+        if k == 0:
+            searched = np.ones(nb, bool)
+        else:
+            m = 1 << k
+            b = np.arange(nb)
+            bx, by, bz = b // (m * m), (b // m) % m, b % m
+            parent = ((bx // 2) * (m // 2) + by // 2) * (m // 2) + bz // 2
+            searched = prev[parent]
+        idx = np.nonzero(searched)[0]
+        if idx.size:
+            sub = Y[torch.as_tensor(idx, device=Y.device)].contiguous()
+            errs = ncp_search(sub, degree, lo, hi)
+            ns, cx = ncp_select(errs, lo, bound, metric)
+            nstar[idx], cplx[idx] = ns, cx
+        models = uniform_models(np.repeat(nstar[:, None], 3, 1), np.full(nb, degree))
+        fit(models, Y.shape[1:], Y.contiguous())
+        out.append(dict(ncp_star=nstar, complex=cplx, searched=searched, models=models))
+        prev = cplx
+    return out
 
 
 class FADecode(torch.autograd.Function):

@@ -370,4 +370,168 @@ fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctr
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
+
+fa_status fa_fit_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
+                        const int32_t res[3], const float *samples, float *ctrl, void *stream) {
+    if (!blocks || nblocks <= 0 || !knots || !res_ok(res) || !samples || !ctrl)
+        return FA_ERR_INVALID_ARG;
+    if (!res_supported(res) || res[1] > 64 || res[2] > 64) return FA_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_adjoint(blocks, nblocks, knots, res[0], res[1], res[2], 1u, samples,
+                                  ctrl, 2, s);
+    if (e == hipSuccess) e = launch_fit_solve(blocks, nblocks, knots, res[0], res[1], res[2], ctrl, s);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+fa_status fa_model_errors(const fa_block *blocks, int32_t nblocks, const float *knots,
+                          const void *ctrl, fa_dtype dtype, const int32_t res[3],
+                          const float *samples, float *decoded, float *errs,
+                          int64_t errs_stride, void *stream) {
+    if (!blocks || nblocks <= 0 || !knots || !ctrl || !res_ok(res) || !samples || !decoded ||
+        !errs || errs_stride < 2)
+        return FA_ERR_INVALID_ARG;
+    if (dtype != FA_F32 && dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const fa_status st = fa_decode_blocks(blocks, nblocks, knots, ctrl, dtype, res, 1u, nullptr,
+                                          nullptr, nullptr, 0, decoded, stream);
+    if (st != FA_OK) return st;
+    const int64_t vox = (int64_t)res[0] * res[1] * res[2];
+    hipError_t e = launch_residual(samples, decoded, vox, nblocks, errs, errs_stride, s);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
+namespace {
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct SearchLayout {
+    int64_t desc, knots, ctrl, decoded, total, cstride;
+};
+
+SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree,
+                           int32_t ncp_hi) {
+    SearchLayout L{};
+    const int64_t vox = (int64_t)res[0] * res[1] * res[2];
+    L.cstride = align_up((int64_t)ncp_hi * ncp_hi * ncp_hi, 64);
+    L.desc = 0;
+    L.knots = align_up(L.desc + (int64_t)nblocks * (int64_t)sizeof(fa_block), 256);
+    L.ctrl = align_up(L.knots + 3 * (int64_t)(ncp_hi + degree + 1) * 4, 256);
+    L.decoded = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
+    L.total = align_up(L.decoded + (int64_t)nblocks * vox * 4, 256);
+    return L;
+}
+
+bool search_args_ok(int32_t nblocks, const int32_t res[3], int32_t degree, int32_t ncp_lo,
+                    int32_t ncp_hi) {
+    if (nblocks <= 0 || !res_ok(res) || degree < 1 || ncp_lo < degree + 1 || ncp_hi < ncp_lo)
+        return false;
+    for (int a = 0; a < 3; ++a)
+        if (ncp_hi > res[a]) return false;  // full column rank needs ncp <= res
+    return true;
+}
+
+bool search_supported(const int32_t res[3], int32_t degree, int32_t ncp_hi) {
+    return degree <= FA_MAX_DEGREE && ncp_hi <= FA_MAX_NCP && res_supported(res) &&
+           res[1] <= 64 && res[2] <= 64;
+}
+}  // namespace
+
+int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t degree,
+                                int32_t ncp_hi) {
+    if (nblocks <= 0 || !res_ok(res) || degree < 1 || ncp_hi < degree + 1) return -1;
+    return search_layout(nblocks, res, degree, ncp_hi).total;
+}
+
+fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res[3],
+                        int32_t degree, int32_t ncp_lo, int32_t ncp_hi, float *errs,
+                        void *workspace, int64_t workspace_bytes, void *stream) {
+    if (!samples || !errs || !workspace || !search_args_ok(nblocks, res, degree, ncp_lo, ncp_hi))
+        return FA_ERR_INVALID_ARG;
+    if (!search_supported(res, degree, ncp_hi)) return FA_ERR_UNSUPPORTED;
+    const SearchLayout L = search_layout(nblocks, res, degree, ncp_hi);
+    if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return FA_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = static_cast<char *>(workspace);
+    fa_block *desc = reinterpret_cast<fa_block *>(w + L.desc);
+    float *knots = reinterpret_cast<float *>(w + L.knots);
+    float *ctrl = reinterpret_cast<float *>(w + L.ctrl);
+    float *decoded = reinterpret_cast<float *>(w + L.decoded);
+    const int ncand = ncp_hi - ncp_lo + 1;
+    // from the largest NCP down, as the in-level search runs (Sec. 4.2.1)
+    for (int n = ncp_hi; n >= ncp_lo; --n) {
+        hipError_t e = launch_candidate(desc, knots, nblocks, n, degree, L.cstride, s);
+        if (e != hipSuccess) return FA_ERR_DEVICE;
+        fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, stream);
+        if (st != FA_OK) return st;
+        st = fa_model_errors(desc, nblocks, knots, ctrl, FA_F32, res, samples, decoded,
+                             errs + 2 * (n - ncp_lo), 2 * (int64_t)ncand, stream);
+        if (st != FA_OK) return st;
+    }
+    return FA_OK;
+}
+
+fa_status fa_ncp_select(const float *errs, int32_t nblocks, int32_t ncand, int32_t ncp_lo,
+                        int32_t metric, float bound, int32_t *ncp_star, int32_t *complex_) {
+    if (!errs || nblocks <= 0 || ncand <= 0 || (metric != 0 && metric != 1) || !ncp_star ||
+        !std::isfinite(bound))
+        return FA_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const float *eb = errs + (int64_t)b * ncand * 2 + metric;
+        int best = -1;
+        bool over = false;
+        for (int c = 0; c < ncand; ++c) {
+            const float v = eb[2 * c];
+            if (best < 0 && v < bound) best = c;
+            if (v > bound) over = true;
+        }
+        ncp_star[b] = ncp_lo + (best >= 0 ? best : ncand - 1);
+        if (complex_) complex_[b] = over ? 1 : 0;
+    }
+    return FA_OK;
+}
+
+fa_status fa_uniform_layout(int32_t nblocks, const int32_t *ncp, const int32_t *degree,
+                            fa_block *blocks, float *knots, int64_t knot_capacity,
+                            int64_t *nknots, int64_t *nctrl) {
+    if (nblocks <= 0 || !ncp || !degree || !nknots || !nctrl) return FA_ERR_INVALID_ARG;
+    int64_t ko = 0, co = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const int p = degree[3 * b];
+        if (p < 1 || degree[3 * b + 1] != p || degree[3 * b + 2] != p) return FA_ERR_INVALID_ARG;
+        int64_t clen = 1;
+        for (int a = 0; a < 3; ++a) {
+            const int n = ncp[3 * b + a];
+            if (n < p + 1) return FA_ERR_INVALID_ARG;
+            clen *= n;
+        }
+        co = align_up(co, 64);
+        if (blocks) {
+            fa_block d{};
+            for (int a = 0; a < 3; ++a) {
+                d.ncp[a] = ncp[3 * b + a];
+                d.degree[a] = p;
+            }
+            d.knot_off = ko;
+            d.ctrl_off = co;
+            d.scale = 1.0f;
+            d.flags = FA_FLAG_UNIFORM_X | FA_FLAG_UNIFORM_Y | FA_FLAG_UNIFORM_Z;
+            blocks[b] = d;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const int n = ncp[3 * b + a];
+            if (knots) {
+                if (ko + n + p + 1 > knot_capacity) return FA_ERR_INVALID_ARG;
+                for (int j = 0; j < n + p + 1; ++j)
+                    knots[ko + j] = j <= p ? 0.0f
+                                           : (j >= n ? 1.0f : (float)(j - p) / (float)(n - p));
+            }
+            ko += n + p + 1;
+        }
+        co += clen;
+    }
+    *nknots = ko;
+    *nctrl = align_up(co, 64);
+    return FA_OK;
+}
 }  // extern "C"

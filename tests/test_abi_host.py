@@ -216,3 +216,65 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
     assert L.fa_decode_blocks_plain(vp, 1, vp, None, r, 15, vp, None) == 1
+
+
+def test_uniform_layout_matches_input_packing(fa):
+    """fa_uniform_layout: knots equal the clamped uniform knots of the input
+    generator, lattices at 64-element offsets, descriptors validate."""
+    ncp = np.array([[5, 7, 9], [4, 4, 4], [33, 12, 64]], np.int32)
+    deg = np.array([[3, 3, 3], [2, 2, 2], [3, 3, 3]], np.int32)
+    nk, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    desc = np.zeros(3, fa.BLOCK_DTYPE)
+    knots = np.zeros(1000, np.float32)
+    assert fa.lib.fa_uniform_layout(3, ncp.ctypes.data, deg.ctypes.data, desc.ctypes.data,
+                                    knots.ctypes.data, knots.size, ctypes.byref(nk),
+                                    ctypes.byref(nc)) == 0
+    b = fi.pack(ncp, deg, [[fi.clamped_uniform_knots(n, d[0]) for n in c]
+                           for c, d in zip(ncp, deg)], [np.zeros(c) for c in ncp])
+    assert nk.value == b.knots.size
+    assert np.array_equal(knots[:nk.value], b.knots)
+    assert np.array_equal(desc["ctrl_off"], b.ctrl_off)
+    assert np.array_equal(desc["knot_off"], b.knot_off)
+    assert nc.value >= b.ctrl_off[-1] + np.prod(ncp[-1])
+    fa.fa_validate_blocks(desc.copy(), knots[:nk.value], nc.value)
+    # capacity and shape errors
+    assert fa.lib.fa_uniform_layout(3, ncp.ctypes.data, deg.ctypes.data, None,
+                                    knots.ctypes.data, 10, ctypes.byref(nk),
+                                    ctypes.byref(nc)) == 1
+    bad = ncp.copy()
+    bad[1, 0] = 2
+    assert fa.lib.fa_uniform_layout(3, bad.ctypes.data, deg.ctypes.data, None, None, 0,
+                                    ctypes.byref(nk), ctypes.byref(nc)) == 1
+
+
+def test_ncp_select_agrees_with_oracle_rule(fa):
+    """fa_ncp_select on seeded error maps == the oracle's Eq. 4 rule."""
+    from oracle import adaptive as ad
+    g = np.random.Generator(np.random.PCG64(5))
+    errs = np.sort(g.uniform(0, 1, (50, 12, 2)), axis=1)[:, ::-1].astype(np.float32)
+    errs[7] = 0.5  # ties with the bound
+    for metric in (0, 1):
+        for bound in (0.05, 0.3, 0.5, 0.99, 2.0):
+            ns, cx = fa.ncp_select(errs, 5, bound, metric)
+            for b in range(50):
+                assert (ns[b], cx[b]) == ad.select_ncp(errs[b].astype(np.float64), 5,
+                                                       np.float32(bound), metric)
+
+
+def test_search_arguments_rejected_without_launch(fa):
+    r = fa._i32x3((16, 16, 16))
+    vp = ctypes.c_void_p(16)
+    assert fa.lib.fa_ncp_search_workspace(4, r, 3, 16) > 4 * 16 ** 3 * 4
+    assert fa.lib.fa_ncp_search_workspace(0, r, 3, 16) == -1
+    ws = fa.lib.fa_ncp_search_workspace(4, r, 3, 16)
+    assert fa.lib.fa_ncp_search(vp, 4, r, 3, 5, 17, vp, ctypes.c_void_p(256), ws, None) == 1
+    assert fa.lib.fa_ncp_search(vp, 4, r, 3, 3, 16, vp, ctypes.c_void_p(256), ws, None) == 1
+    assert fa.lib.fa_ncp_search(vp, 4, r, 3, 5, 16, vp, ctypes.c_void_p(256), ws - 1, None) == 1
+    assert fa.lib.fa_ncp_search(vp, 4, r, 3, 5, 16, vp, ctypes.c_void_p(257), ws, None) == 1
+    assert fa.lib.fa_ncp_search(vp, 4, r, 4, 5, 16, vp, ctypes.c_void_p(256), ws, None) == 2
+    big = fa._i32x3((80, 80, 80))
+    assert fa.lib.fa_ncp_search(vp, 4, big, 3, 5, 70, vp, ctypes.c_void_p(256),
+                                fa.lib.fa_ncp_search_workspace(4, big, 3, 70), None) == 2
+    assert fa.lib.fa_fit_blocks(vp, 1, vp, fa._i32x3((64, 65, 64)), vp, vp, None) == 2
+    assert fa.lib.fa_fit_blocks(None, 1, vp, r, vp, vp, None) == 1
+    assert fa.lib.fa_model_errors(vp, 1, vp, vp, 0, r, vp, vp, vp, 1, None) == 1
