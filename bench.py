@@ -35,6 +35,14 @@ KERNEL_SOURCES = {
                     "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "adjoint": ["paper_2409_00184_amd/csrc/fa_adjoint.hip",
                 "paper_2409_00184_amd/csrc/fa_device.hpp"],
+    "ncp_search": ["paper_2409_00184_amd/csrc/fa_fit.hip",
+                   "paper_2409_00184_amd/csrc/fa_adjoint.hip",
+                   "paper_2409_00184_amd/csrc/fa_decode.hip",
+                   "paper_2409_00184_amd/csrc/fa_device.hpp"],
+    "fit_decode": ["paper_2409_00184_amd/csrc/fa_fit.hip",
+                   "paper_2409_00184_amd/csrc/fa_adjoint.hip",
+                   "paper_2409_00184_amd/csrc/fa_decode.hip",
+                   "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "render": ["paper_2409_00184_amd/csrc/fa_render.hip", "paper_2409_00184_amd/csrc/fa_eval.hpp",
                "paper_2409_00184_amd/csrc/fa_device.hpp"],
 }
@@ -423,6 +431,209 @@ def bench_f1(args):
     return line
 
 
+# ------------------------------------------------------------------ F2
+
+def bench_f2(args):
+    """In-level adaptive NCP search (Sec. 4.2.1, the inner loop of Alg. 1):
+    64 micro-blocks of 64^3 FP32 samples, degree 3, every NCP from 64 down
+    to 5 fitted (least squares), decoded and scored; one step = the whole
+    search (60 candidate fits per block)."""
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    R, p, nb = 64, 3, 64
+    lo, hi = p + 2, R
+    ncand = hi - lo + 1
+    Y = torch.as_tensor(fi.turbulence_cube(fi.rng(12), R, nb)).cuda().contiguous()
+    ws = torch.empty(fa.lib.fa_ncp_search_workspace(nb, fa._i32x3((R, R, R)), p, hi),
+                     dtype=torch.uint8, device="cuda")
+    errs = torch.empty((nb, ncand, 2), device="cuda")
+    st = lambda: fa.lib.fa_ncp_search(fa._ptr(Y), nb, fa._i32x3((R, R, R)), p, lo, hi,
+                                      fa._ptr(errs), fa._ptr(ws), ws.numel(), fa._stream())
+    run = lambda: fa._check("fa_ncp_search", st())
+    stream = torch.cuda.current_stream()
+    graph, _ = fa.capture(run)
+    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph
+    # per-stage breakdown at a few NCPs (fit = adjoint + Gram solve; errors =
+    # value decode + residual reduction), HIP events on the launch stream
+    stages = {}
+    for n in (8, 32, 64):
+        m = fa.uniform_models(np.full((nb, 3), n), np.full(nb, p))
+        dec = torch.empty_like(Y)
+        f_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y), 5, 2, stream)[1]
+        e_ms = timed_steps(lambda: fa.model_errors(m, (R, R, R), Y, decoded=dec), 5, 2,
+                           stream)[1]
+        stages[str(n)] = {"fit_ms": f_ms, "errors_ms": e_ms}
+        del m, dec
+    vox = nb * R ** 3
+    # HBM floor of the four passes over the voxels per candidate: the adjoint
+    # reads y, the decode writes f, the residual reads y and f (16 B/voxel)
+    alg = ncand * vox * 16
+    line = _common(args, "micro-blocks searched/sec (adaptive NCP, Eq. 4)", nb / (ms * 1e-3),
+                   "blocks/s", ms, "f32",
+                   "F2 in-level adaptive NCP search: 64 micro-blocks of 64^3 FP32 samples "
+                   "(k^-5/3 turbulence), degree 3, NCP 64..5 (60 least-squares fits, decodes "
+                   "and error reductions per block)",
+                   {"roofline": _roof(alg, ev_ms, "ncp_search", "f2"),
+                    "fits_per_s": nb * ncand / (ms * 1e-3),
+                    "stages_at_ncp": stages})
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import adaptive as ad
+        y0 = Y[0].double().cpu().numpy()
+        t0 = time.perf_counter()
+        k = 0
+        for n in range(hi, lo - 1, -1):
+            kn = [ad.uniform_knots(n, p)] * 3
+            P = ad.fit_block(y0, (n, n, n), (p, p, p), kn)
+            ad.model_errors(y0, P, (n, n, n), (p, p, p), kn)
+            k += 1
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": k / ncand / dt, "unit": "blocks/s",
+                                "cores": oracle.nthreads_default(), "kind": "oracle",
+                                "sample": f"{k} of the {ncand} candidate fits of one 64^3 block "
+                                          f"(from NCP 64 down), FP64 least squares + decode, "
+                                          f"{dt:.1f} s"}
+    return line
+
+
+# ------------------------------------------------------------------ F4
+
+def ml_level_samples(level, R, blocks, torch, device="cuda"):
+    """FP32 Marschner-Lobb samples [len(blocks), R, R, R] of one pyramid level,
+    generated on the GPU in FP64 (same recipe as fa_inputs.ml_blocks)."""
+    import fa_inputs as fi
+    m = 1 << level
+    b = torch.as_tensor(blocks, device=device)
+    u = torch.arange(R, dtype=torch.float64, device=device) / (R - 1)
+    h = fi.ML_EXTENT / m
+    bx = (b // (m * m)).double()
+    by = ((b // m) % m).double()
+    bz = (b % m).double()
+    x = (h * (bx[:, None] + u[None]))[:, :, None, None]
+    y = (h * (by[:, None] + u[None]))[:, None, :, None]
+    z = (h * (bz[:, None] + u[None]))[:, None, None, :]
+    return fi.ml_value(x, y, z, xp=torch).float().contiguous()
+
+
+def bench_f4(args):
+    """Marschner-Lobb end to end (Eq. 5): level 4 of the pyramid (16^3
+    micro-blocks of 64^3 samples with shared faces = a 1009^3 grid over
+    [0,7]^3), FAM encode (least-squares fit at NCP 32) + decode of value and
+    gradient; quality against the analytic field, and the adaptive encoding
+    (in-level search, Eq. 4) beside it."""
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    level, R, p, n_fam = 4, 64, 3, 32
+    nb = (1 << level) ** 3
+    Y = torch.empty((nb, R, R, R), device="cuda")
+    for b0 in range(0, nb, 256):
+        Y[b0:b0 + 256] = ml_level_samples(level, R, list(range(b0, min(nb, b0 + 256))), torch)
+    m = fa.uniform_models(np.full((nb, 3), n_fam), np.full(nb, p))
+    out = torch.empty((nb, 4, R, R, R), device="cuda")
+    plan = fa.Plan(m, (R, R, R), rows=4, waves=4, grid=1 << 20, store=0)
+
+    def step():
+        fa.fit(m, (R, R, R), Y)
+        fa.decode(m, (R, R, R), 15, plan=plan, out=out)
+
+    stream = torch.cuda.current_stream()
+    graph, _ = fa.capture(step)
+    ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph
+    fit_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y), 5, 2, stream)[1]
+    dec_ms = timed_steps(lambda: fa.decode(m, (R, R, R), 15, plan=plan, out=out), 5, 2,
+                         stream)[1]
+    step()
+    torch.cuda.synchronize()
+
+    def quality(o):
+        """value PSNR (range [0,1]) and gradient relative RMS against Eq. 5."""
+        se_v = se_g = ng = 0.0
+        dudx = (1 << level) / fi.ML_EXTENT
+        u = torch.arange(R, dtype=torch.float64, device="cuda") / (R - 1)
+        h = fi.ML_EXTENT / (1 << level)
+        for b0 in range(0, nb, 256):
+            b = torch.arange(b0, min(nb, b0 + 256), device="cuda")
+            mm = 1 << level
+            x = (h * ((b // (mm * mm)).double()[:, None] + u[None]))[:, :, None, None]
+            y = (h * (((b // mm) % mm).double()[:, None] + u[None]))[:, None, :, None]
+            z = (h * ((b % mm).double()[:, None] + u[None]))[:, None, None, :]
+            v = fi.ml_value(x, y, z, xp=torch)
+            g = fi.ml_gradient(x, y, z, xp=torch)
+            ob = o[b0:b0 + 256].double()
+            se_v += float(((ob[:, 0] - v) ** 2).sum())
+            for a in range(3):
+                se_g += float(((ob[:, 1 + a] * dudx - g[a]) ** 2).sum())
+                ng += float((g[a] ** 2).sum())
+        mse = se_v / (nb * R ** 3)
+        return {"value_psnr_db": 10 * np.log10(1.0 / mse), "value_rmse": mse ** 0.5,
+                "grad_rel_rms": (se_g / ng) ** 0.5}
+
+    q_fam = quality(out)
+    sizes = lambda ncp: float(np.sum(1 + (3 * (ncp + p) + ncp.astype(np.float64) ** 3) * 4))
+    raw = nb * R ** 3 * 4
+    fam = dict(q_fam, ncp=n_fam, bytes=sizes(np.full(nb, n_fam)),
+               compression=raw / sizes(np.full(nb, n_fam)))
+    # adaptive (Eq. 4): in-level search on every block of the level, RMS bound
+    bound = 2e-3
+    t0 = time.perf_counter()
+    errs = fa.ncp_search(Y, p, p + 2, 40)
+    torch.cuda.synchronize()
+    search_s = time.perf_counter() - t0
+    nstar, cplx = fa.ncp_select(errs, p + 2, bound)
+    ma = fa.uniform_models(np.repeat(nstar[:, None], 3, 1), np.full(nb, p))
+    fa.fit(ma, (R, R, R), Y)
+    fa.decode(ma, (R, R, R), 15, out=out)
+    torch.cuda.synchronize()
+    adaptive = dict(quality(out), rms_bound=bound, ncp_mean=float(nstar.mean()),
+                    ncp_hist={int(k): int(v) for k, v in zip(*np.unique(nstar,
+                                                                        return_counts=True))},
+                    complex_blocks=int(cplx.sum()), bytes=sizes(nstar),
+                    compression=raw / sizes(nstar), search_s=search_s,
+                    search_candidates="5..40")
+    vox = nb * R ** 3
+    line = _common(args, "encoded+decoded voxels/sec (Marschner-Lobb, FAM fit + value/grad "
+                   "decode)", vox / (ms * 1e-3), "voxels/s", ms, "f32",
+                   "F4 Marschner-Lobb (Eq. 5, f_M 6, alpha 0.05, [0,7]^3): 16^3 micro-blocks "
+                   "of 64^3 samples (1009^3 grid), least-squares fit at NCP 32 + decode of "
+                   "value and gradient, FP32; quality vs the analytic field",
+                   {"roofline": _roof(vox * 4 + vox * 16 + 8 * m.ctrl.numel(), ev_ms,
+                                      "fit_decode", "f4"),
+                    "stages": {"fit_ms": fit_ms, "decode_ms": dec_ms},
+                    "quality": {"fam": fam, "adaptive": adaptive}})
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import adaptive as ad
+        y0 = Y[0].double().cpu().numpy()
+        kn = [ad.uniform_knots(n_fam, p)] * 3
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            P = ad.fit_block(y0, (n_fam,) * 3, (p,) * 3, kn)
+            ob = oracle.Blocks(np.array([[n_fam] * 3]), np.array([[p] * 3]), np.zeros(1),
+                               np.zeros(1), np.concatenate(kn), P.reshape(-1))
+            oracle.decode_blocks(ob, (R, R, R), 15)
+            k += 1
+            if time.perf_counter() - t0 > min(args.cpu_seconds, 10.0):
+                break
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": k * R ** 3 / dt, "unit": "voxels/s",
+                                "cores": oracle.nthreads_default(), "kind": "oracle",
+                                "sample": f"{k} x block 0 (64^3): FP64 least-squares fit at "
+                                          f"NCP 32 + value/gradient decode, {dt:.1f} s"}
+    del Y, out
+    return line
+
+
 # ------------------------------------------------------------------ C4
 
 def bench_c4(args):
@@ -562,7 +773,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1", "f2", "f4"])
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
@@ -590,7 +801,8 @@ def main():
         probe(args)
         return
     line = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-            "c5": bench_c5, "f1": bench_f1}[args.workload](args)
+            "c5": bench_c5, "f1": bench_f1,
+            "f2": bench_f2, "f4": bench_f4}[args.workload](args)
     print(json.dumps(line), flush=True)
 
 

@@ -15,6 +15,10 @@ Recipes (all seeded with numpy.random.Generator(PCG64(seed))):
 * turbulence field: random-phase Fourier modes on a periodic m^3 grid with
   shell energy E(k) ~ k^(-5/3), i.e. mode amplitude ~ |k|^(-11/6), 1 <= |k|
   up to Nyquist, normalised to zero mean and unit variance, FP32.
+* Marschner-Lobb field (Eq. 5) with f_M = 6, alpha = 0.05 on [0, 7]^3, and
+  its analytic gradient (the ground truth of the quality workload).
+* pyramids of micro-blocks: level k tiles the domain with (2^k)^3 blocks
+  sharing their boundary samples, each sampled on its own R^3 grid.
 """
 import math
 from dataclasses import dataclass, field
@@ -322,3 +326,54 @@ def config_c5(seed=5, nblocks=4096, n=32, p=3):
                [[t, t, t]] * nblocks, list(P))
     out.meta.update(config="C5", res=(64, 64, 64))
     return out
+
+
+# ----------------------------------------------------------- Marschner-Lobb
+
+ML_FM, ML_ALPHA, ML_EXTENT = 6.0, 0.05, 7.0
+
+
+def ml_value(x, y, z, fm=ML_FM, alpha=ML_ALPHA, xp=np):
+    """F = (1 - sin(pi z / 2) + alpha (1 + rho(sqrt(x^2 + y^2)))) / (2 (1 + alpha)),
+    rho(r) = cos(2 pi f_M cos(pi r / 2))  (Eq. 5).  xp: numpy or torch."""
+    r = xp.sqrt(x * x + y * y)
+    rho = xp.cos(2.0 * math.pi * fm * xp.cos(math.pi * r / 2.0))
+    return (1.0 - xp.sin(math.pi * z / 2.0) + alpha * (1.0 + rho)) / (2.0 * (1.0 + alpha))
+
+
+def ml_gradient(x, y, z, fm=ML_FM, alpha=ML_ALPHA, xp=np):
+    """(dF/dx, dF/dy, dF/dz) of ml_value, differentiated by hand:
+    drho/dr = pi^2 f_M sin(pi r / 2) sin(2 pi f_M cos(pi r / 2)), and
+    dr/dx = x / r (the x, y derivatives vanish at r = 0)."""
+    c = 1.0 / (2.0 * (1.0 + alpha))
+    r = xp.sqrt(x * x + y * y)
+    drho = math.pi ** 2 * fm * xp.sin(math.pi * r / 2.0) * xp.sin(
+        2.0 * math.pi * fm * xp.cos(math.pi * r / 2.0))
+    safe = xp.where(r > 0, r, xp.ones_like(r))
+    k = xp.where(r > 0, c * alpha * drho / safe, xp.zeros_like(r))
+    gz = -c * (math.pi / 2.0) * xp.cos(math.pi * z / 2.0)
+    return k * x, k * y, gz + 0.0 * x
+
+
+def block_grid(level, b, R, extent=ML_EXTENT, lo=0.0):
+    """Sample coordinates (x [R], y [R], z [R], float64) of block b of level
+    `level` (block (bx, by, bz) at index (bx * m + by) * m + bz, m = 2^level),
+    neighbours sharing boundary samples: x_i = lo + extent (bx + i/(R-1)) / m."""
+    m = 1 << level
+    bx, by, bz = b // (m * m), (b // m) % m, b % m
+    u = np.arange(R, dtype=np.float64) / (R - 1)
+    h = extent / m
+    return lo + h * (bx + u), lo + h * (by + u), lo + h * (bz + u)
+
+
+def ml_blocks(level, R, blocks=None, extent=ML_EXTENT):
+    """FP32 samples [nb, R, R, R] of the Marschner-Lobb field on the blocks
+    of one pyramid level (all blocks, or the listed ones)."""
+    m = 1 << level
+    ids = range(m ** 3) if blocks is None else blocks
+    out = []
+    for b in ids:
+        x, y, z = block_grid(level, b, R, extent)
+        out.append(ml_value(x[:, None, None], y[None, :, None], z[None, None, :]))
+    return np.asarray(out, np.float32)
+
