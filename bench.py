@@ -502,6 +502,84 @@ def bench_f2(args):
     return line
 
 
+# ------------------------------------------------------------------ F3
+
+PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, one direction
+
+
+def bench_f3(args):
+    """Caching and memory copy of Alg. 2 for the C3 camera: the visible
+    micro-models of the view (fa_visible_cells), fetched through the host
+    LRU cache from an Eq. 2 file and staged to the GPU with page-locked
+    asynchronous copies.  Warm frames (the view fits the cache) measure the
+    copy; cold frames and the paper's 200-block cache add file reads."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import fa_inputs as fi
+    import paper_2409_00184_amd as fa
+    nb, p = 16, 3
+    g = fi.rng(13)
+    k, phi = fi.sinusoid_params(g)
+    ncp = g.integers(8, 33, nb ** 3)
+    kl, lat = [], []
+    for b in range(nb ** 3):
+        n = int(ncp[b])
+        ts = [fi.clamped_uniform_knots(n, p)] * 3
+        kl.append(ts)
+        lat.append(np.zeros((n, n, n)) if b % 7 else
+                   fi.sinusoid_lattice(k, phi, ts[0], ts[1], ts[2], (n,) * 3, (p,) * 3))
+    batch = fi.pack(np.repeat(ncp[:, None], 3, 1), np.full((nb ** 3, 3), p), kl, lat)
+    desc = fa.host_descriptors(batch.ncp, batch.deg, batch.knot_off, batch.ctrl_off)
+    tmp = tempfile.mkdtemp()
+    path = os.path.join(tmp, "c3.fam")
+    fa.store_write(path, desc, batch.knots, batch.ctrl)
+    file_bytes = os.path.getsize(path)
+    W, H, S = 1920, 1080, 512
+    rays = torch.as_tensor(fi.render_rays(3, W, H), device="cuda")
+    flags = fa.visible_cells(rays, W, H, S, (nb,) * 3, (0, 0, 0), (1, 1, 1))
+    stream = torch.cuda.current_stream()
+    vis_ms = timed_steps(lambda: fa.visible_cells(rays, W, H, S, (nb,) * 3, (0, 0, 0),
+                                                  (1, 1, 1), out=flags), 5, 2, stream)[1]
+    ids = np.nonzero(flags.cpu().numpy())[0].astype(np.int32)
+    out = {}
+    for name, cache in (("warm", len(ids)), ("paper_cache_200", 200)):
+        store = fa.Store(path, cache_blocks=cache, pinned=True, max_stage=len(ids))
+        store.stage(ids)  # first (cold) frame
+        torch.cuda.synchronize()
+        st0 = store.stage(ids)[1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = store.stage(ids)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        h2d = (st["bytes_h2d"] - st0["bytes_h2d"]) / args.steps
+        out[name] = {"ms_per_frame": dt * 1e3, "h2d_bytes_per_frame": h2d,
+                     "h2d_gbs": h2d / dt / 1e9,
+                     "misses_per_frame": (st["misses"] - st0["misses"]) / args.steps,
+                     "read_bytes_per_frame": (st["bytes_read"] - st0["bytes_read"]) / args.steps}
+        store.close()
+    os.remove(path)
+    os.rmdir(tmp)
+    warm = out["warm"]
+    line = _common(args, "staged micro-model bytes/sec (Alg. 2 caching + copy, warm cache)",
+                   warm["h2d_bytes_per_frame"] / (warm["ms_per_frame"] * 1e-3), "B/s",
+                   warm["ms_per_frame"], "f32",
+                   "F3 caching + copy of the visible micro-models of the C3 view (16^3 "
+                   "cubic micro-models, NCP 8..32, degree 3, Eq. 2 file; 1920x1080 rays x 512 "
+                   "samples for visibility)",
+                   {"roofline": {"bound": "pcie", "achieved": warm["h2d_gbs"],
+                                 "peak": PCIE_PEAK_GBS, "unit": "GB/s",
+                                 "frac": warm["h2d_gbs"] / PCIE_PEAK_GBS, "traffic": None,
+                                 "kernel": "hipMemcpyAsync H2D"},
+                    "visible_blocks": int(len(ids)), "file_bytes": file_bytes,
+                    "visible_cells_ms": vis_ms, "frames": out})
+    return line
+
+
 # ------------------------------------------------------------------ F4
 
 def ml_level_samples(level, R, blocks, torch, device="cuda"):
@@ -773,7 +851,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1", "f2", "f4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1", "f2", "f3", "f4"])
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
@@ -802,7 +880,7 @@ def main():
         return
     line = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
             "c5": bench_c5, "f1": bench_f1,
-            "f2": bench_f2, "f4": bench_f4}[args.workload](args)
+            "f2": bench_f2, "f3": bench_f3, "f4": bench_f4}[args.workload](args)
     print(json.dumps(line), flush=True)
 
 

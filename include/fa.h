@@ -372,6 +372,94 @@ fa_status fa_uniform_layout(int32_t nblocks, const int32_t *ncp, const int32_t *
                             fa_block *blocks, float *knots, int64_t knot_capacity,
                             int64_t *nknots, int64_t *nctrl);
 
+/* ------------------------------------------------------------------ */
+/* Storage, host cache and staging of micro-models (Eq. 2; Alg. 2)     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Visible micro-models of a view, the first step of Alg. 2: flags[cell] = 1
+ * for every cell of the nb[0] x nb[1] x nb[2] tiling that some sample of
+ * fa_render_rays (same rays, same `samples`, same sample positions and
+ * block lookup) falls in, else 0.  The cells a rendering of this view
+ * queries are exactly the flagged ones.
+ *   rays   device fa_ray [height][width]; flags device int32 [ncells]
+ *          (overwritten in full; no memset is used, graph-capturable)
+ * Errors: FA_ERR_INVALID_ARG for null pointers, width/height/samples <= 0,
+ * non-positive or non-finite extent, non-finite origin.
+ */
+fa_status fa_visible_cells(const fa_ray *rays, int32_t width, int32_t height, int32_t samples,
+                           const int32_t nb[3], const float origin[3], const float extent[3],
+                           int32_t *flags, void *stream);
+
+/*
+ * Micro-model file (Eq. 2).  Header: "FAM1", int32 version (1), int32
+ * nblocks, int32 0; index: int64 offset, int64 size per block; records:
+ * one byte (degree p), for x, y, z the clamped knot vector without its last
+ * knot (NCP + p FP32 values; the last knot of a clamped vector on [0, 1] is
+ * 1), then the NCP^3 FP32 control points [x][y][z].  A record therefore
+ * takes exactly 1 + ((NCP + p) * 3 + NCP^3) * 4 bytes, and NCP is recovered
+ * from its size.  One NCP and one degree per block (as Eq. 2 counts them):
+ * blocks with unequal NCP or degree per axis are FA_ERR_INVALID_ARG.
+ *   blocks, knots, ctrl  host arrays (FP32 lattices)
+ * FA_ERR_DEVICE on an I/O error.
+ */
+fa_status fa_store_write(const char *path, int32_t nblocks, const fa_block *blocks,
+                         const float *knots, const float *ctrl);
+
+typedef struct fa_store fa_store;  /* opaque: an open file plus its host cache */
+
+#define FA_STORE_PINNED 1u  /* page-locked cache slots (required by fa_store_stage) */
+
+typedef struct fa_store_stats {
+    int64_t hits, misses, evictions;  /* cache lookups since fa_store_open   */
+    int64_t bytes_read;               /* record bytes read from the file     */
+    int64_t bytes_h2d;                /* bytes copied to the device (stage)  */
+} fa_store_stats;
+
+/*
+ * Open a micro-model file with a host cache of `cache_blocks` slots (each
+ * large enough for the file's largest record).  With FA_STORE_PINNED the
+ * slots are page-locked (hipHostMalloc) so staging copies are DMA
+ * transfers.  Allocates; not for hot loops.  FA_ERR_INVALID_ARG for a
+ * missing or malformed file.
+ */
+fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, fa_store **out);
+fa_status fa_store_close(fa_store *s);
+
+/* Block count and per-block NCP and degree (arrays of nblocks, may be null). */
+fa_status fa_store_info(const fa_store *s, int32_t *nblocks, int32_t *ncp, int32_t *degree);
+
+/*
+ * The caching step of Alg. 2 on the host: for ids[0..n) in order, a cached
+ * block is a hit (and becomes the most recently used), a missing one is
+ * read from the file into a free slot or, with the cache full, into the
+ * slot of the least recently used block.  slots[i] (may be null) receives
+ * the slot holding ids[i] at the time it was looked up (a later lookup in
+ * the same call can evict it when n exceeds the cache).  stats (may be null)
+ * receives the running counters.
+ */
+fa_status fa_store_fetch(fa_store *s, const int32_t *ids, int32_t n, int32_t *slots,
+                         fa_store_stats *stats);
+
+/* Host view of a cache slot: block id, its 3 full knot vectors (x, y, z
+ * back to back, last knot included) and its lattice. */
+fa_status fa_store_slot(const fa_store *s, int32_t slot, int32_t *block, const float **knots,
+                        const float **ctrl);
+
+/*
+ * Caching plus memory copy of Alg. 2: blocks ids[0..n) are fetched as by
+ * fa_store_fetch and copied, as they are fetched, into a packed device batch
+ * on `stream`: descriptor i = block ids[i] with knots at dev_knots[knot_off]
+ * and its lattice at dev_ctrl[ctrl_off] (64-element aligned), uniform-knot
+ * flags set as fa_validate_blocks would.  Asynchronous; the cache keeps a
+ * slot from being refilled while a copy from it may still run.  Requires a
+ * store opened with FA_STORE_PINNED.  FA_ERR_INVALID_ARG for bad ids, n >
+ * nblocks of the file, or capacities below the batch's knot/lattice counts.
+ */
+fa_status fa_store_stage(fa_store *s, const int32_t *ids, int32_t n, fa_block *dev_blocks,
+                         float *dev_knots, int64_t knot_capacity, float *dev_ctrl,
+                         int64_t ctrl_capacity, fa_store_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,15 @@ class FARenderParams(ctypes.Structure):
                 ("shininess", ctypes.c_float), ("grad_min", ctypes.c_float)]
 
 
+class FAStoreStats(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_int64), ("misses", ctypes.c_int64),
+                ("evictions", ctypes.c_int64), ("bytes_read", ctypes.c_int64),
+                ("bytes_h2d", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class FAError(RuntimeError):
     def __init__(self, call, status):
         self.status = status
@@ -104,6 +113,23 @@ def _load():
     L.fa_ncp_select.argtypes = [vp, i32, i32, i32, i32, ctypes.c_float, vp, vp]
     L.fa_uniform_layout.restype = ctypes.c_int
     L.fa_uniform_layout.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp]
+    L.fa_visible_cells.restype = ctypes.c_int
+    L.fa_visible_cells.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    L.fa_store_write.restype = ctypes.c_int
+    L.fa_store_write.argtypes = [ctypes.c_char_p, i32, vp, vp, vp]
+    L.fa_store_open.restype = ctypes.c_int
+    L.fa_store_open.argtypes = [ctypes.c_char_p, i32, u32, ctypes.POINTER(vp)]
+    L.fa_store_close.restype = ctypes.c_int
+    L.fa_store_close.argtypes = [vp]
+    L.fa_store_info.restype = ctypes.c_int
+    L.fa_store_info.argtypes = [vp, vp, vp, vp]
+    L.fa_store_fetch.restype = ctypes.c_int
+    L.fa_store_fetch.argtypes = [vp, vp, i32, vp, vp]
+    L.fa_store_slot.restype = ctypes.c_int
+    L.fa_store_slot.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_float)),
+                                ctypes.POINTER(ctypes.POINTER(ctypes.c_float))]
+    L.fa_store_stage.restype = ctypes.c_int
+    L.fa_store_stage.argtypes = [vp, vp, i32, vp, vp, i64, vp, i64, vp, vp]
     L.fa_decode_backward.restype = ctypes.c_int
     L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
     L.fa_quantize_blocks.restype = ctypes.c_int
@@ -447,6 +473,125 @@ def adaptive_encode(levels, degree, bound, metric=METRIC_RMS, ncp_lo=None, ncp_h
         out.append(dict(ncp_star=nstar, complex=cplx, searched=searched, models=models))
         prev = cplx
     return out
+
+
+# ------------------------------------------------- storage, cache, staging
+
+FA_STORE_PINNED = 1
+
+
+def visible_cells(rays, width, height, samples, nb, origin, extent, out=None, stream=None):
+    """int32 flags [ncells]: cells some sample of render() looks up (fa_visible_cells)."""
+    assert rays.dtype == torch.float32 and rays.is_contiguous()
+    assert rays.numel() == 8 * int(width) * int(height)
+    if out is None:
+        out = torch.empty(int(np.prod(nb)), dtype=torch.int32, device=rays.device)
+    st = lib.fa_visible_cells(_ptr(rays), int(width), int(height), int(samples), _i32x3(nb),
+                              _f32x3(origin), _f32x3(extent), _ptr(out), _stream(stream))
+    _check("fa_visible_cells", st)
+    return out
+
+
+def store_write(path, host_desc, knots, ctrl):
+    """Write micro-models (host descriptors, FP32 knots and lattices) to a
+    file in the Eq. 2 record format (fa_store_write)."""
+    knots = np.ascontiguousarray(knots, np.float32)
+    ctrl = np.ascontiguousarray(ctrl, np.float32)
+    desc = np.ascontiguousarray(host_desc)
+    st = lib.fa_store_write(os.fsencode(path), len(desc), desc.ctypes.data, knots.ctypes.data,
+                            ctrl.ctypes.data)
+    _check("fa_store_write", st)
+
+
+class StagedModels:
+    """A device batch filled by Store.stage(): the same interface as
+    MicroModels for decode/query/render (FP32 lattices)."""
+
+    def __init__(self, desc, knots, ctrl, nblocks, device):
+        self.desc, self.knots, self.ctrl = desc, knots, ctrl
+        self.nblocks, self.device = nblocks, device
+
+    def lattice(self, dtype="f32", stream=None):
+        if dtype != "f32":
+            raise ValueError("staged micro-models are FP32")
+        return self.desc, self.ctrl
+
+
+class Store:
+    """An open micro-model file with a host LRU cache (fa_store_*)."""
+
+    def __init__(self, path, cache_blocks=200, pinned=True, max_stage=None, device="cuda"):
+        h = ctypes.c_void_p()
+        st = lib.fa_store_open(os.fsencode(path), int(cache_blocks),
+                               FA_STORE_PINNED if pinned else 0, ctypes.byref(h))
+        _check("fa_store_open", st)
+        self.h = h
+        n = ctypes.c_int32(0)
+        _check("fa_store_info", lib.fa_store_info(h, ctypes.byref(n), None, None))
+        self.nblocks = n.value
+        self.ncp = np.zeros(self.nblocks, np.int32)
+        self.degree = np.zeros(self.nblocks, np.int32)
+        _check("fa_store_info", lib.fa_store_info(h, None, self.ncp.ctypes.data,
+                                                  self.degree.ctypes.data))
+        self.device = torch.device(device)
+        self.max_stage = self.nblocks if max_stage is None else int(max_stage)
+        self._arena = None
+
+    def close(self):
+        if self.h:
+            _check("fa_store_close", lib.fa_store_close(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fetch(self, ids):
+        """Caching step on the host: (slots [n], stats dict)."""
+        ids = np.ascontiguousarray(ids, np.int32)
+        slots = np.zeros(ids.size, np.int32)
+        stats = FAStoreStats()
+        st = lib.fa_store_fetch(self.h, ids.ctypes.data, ids.size, slots.ctypes.data,
+                                ctypes.byref(stats))
+        _check("fa_store_fetch", st)
+        return slots, stats.as_dict()
+
+    def slot(self, slot):
+        """(block, knots [3 vectors], lattice [n, n, n]) copies of one slot."""
+        b = ctypes.c_int32(0)
+        kp = ctypes.POINTER(ctypes.c_float)()
+        cp = ctypes.POINTER(ctypes.c_float)()
+        _check("fa_store_slot", lib.fa_store_slot(self.h, int(slot), ctypes.byref(b),
+                                                  ctypes.byref(kp), ctypes.byref(cp)))
+        n, p = int(self.ncp[b.value]), int(self.degree[b.value])
+        kn = np.ctypeslib.as_array(kp, shape=(3 * (n + p + 1),)).copy()
+        P = np.ctypeslib.as_array(cp, shape=(n * n * n,)).copy().reshape(n, n, n)
+        return b.value, kn.reshape(3, n + p + 1), P
+
+    def _arena_for(self):
+        if self._arena is None:
+            order = np.sort(self.ncp.astype(np.int64) ** 3)[::-1][:self.max_stage]
+            kcap = int(np.sort(3 * (self.ncp + self.degree + 1))[::-1][:self.max_stage].sum())
+            ccap = int(((order + 63) // 64 * 64).sum())
+            self._arena = (
+                torch.zeros(self.max_stage * BLOCK_DTYPE.itemsize, dtype=torch.uint8,
+                            device=self.device),
+                torch.zeros(max(kcap, 1), dtype=torch.float32, device=self.device),
+                torch.zeros(max(ccap, 64), dtype=torch.float32, device=self.device))
+        return self._arena
+
+    def stage(self, ids, stream=None):
+        """Caching + copy to the GPU (fa_store_stage) -> (StagedModels, stats)."""
+        ids = np.ascontiguousarray(ids, np.int32)
+        assert 0 < ids.size <= self.max_stage
+        d, k, c = self._arena_for()
+        stats = FAStoreStats()
+        st = lib.fa_store_stage(self.h, ids.ctypes.data, ids.size, _ptr(d), _ptr(k), k.numel(),
+                                _ptr(c), c.numel(), ctypes.byref(stats), _stream(stream))
+        _check("fa_store_stage", st)
+        return StagedModels(d, k, c, int(ids.size), self.device), stats.as_dict()
 
 
 class FADecode(torch.autograd.Function):

@@ -348,6 +348,28 @@ fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t 
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
+fa_status fa_visible_cells(const fa_ray *rays, int32_t width, int32_t height, int32_t samples,
+                           const int32_t nb[3], const float origin[3], const float extent[3],
+                           int32_t *flags, void *stream) {
+    if (!rays || width <= 0 || height <= 0 || samples <= 0 || !nb || !origin || !extent ||
+        !flags)
+        return FA_ERR_INVALID_ARG;
+    int n[3];
+    float o[3], r[3];
+    for (int k = 0; k < 3; ++k) {
+        if (nb[k] <= 0 || !(extent[k] > 0.0f) || !std::isfinite(origin[k]) ||
+            !std::isfinite(extent[k]))
+            return FA_ERR_INVALID_ARG;
+        n[k] = nb[k];
+        o[k] = origin[k];
+        r[k] = (float)nb[k] / extent[k];
+    }
+    if ((int64_t)nb[0] * nb[1] * nb[2] > (int64_t)1 << 30) return FA_ERR_UNSUPPORTED;
+    hipError_t e = launch_visible(rays, (int64_t)width * height, samples, n, o, r, flags,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
                              const int32_t res[3], uint32_t mask, const float *grad_out,
                              float *grad_ctrl, int32_t rows_per_item, void *stream) {

@@ -62,6 +62,10 @@ hipError_t launch_render(const QueryLaunch &q, const fa_ray *rays, int width, in
                          const fa_render_params &p, const float *tf, float *image,
                          hipStream_t s);
 
+hipError_t launch_visible(const fa_ray *rays, int64_t nrays, int samples, const int nb[3],
+                          const float origin[3], const float rscale[3], int32_t *flags,
+                          hipStream_t s);
+
 hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
                           int ry, int rz, uint32_t mask, const float *g, float *G, int it,
                           hipStream_t s);

@@ -8,6 +8,8 @@
 // sample index its 64 rays lie within a pixel footprint of each other, so
 // they mostly share a micro-model and knot spans and their lattice gathers
 // hit the same cache lines.  A wave stops when all of its rays have.
+#include <algorithm>
+
 #include "fa_eval.hpp"
 
 namespace fa {
@@ -90,7 +92,68 @@ __global__ __launch_bounds__(256) void render_kernel(RenderLaunch a) {
     }
 }
 
+// Visible micro-models of a view (Alg. 2): flags[cell] = 1 for every cell
+// that a sample of fa_render_rays would look up (same sample positions,
+// same lookup), 0 for the others.  One thread per (ray, chunk of samples);
+// a thread stores only when its cell changes along the ray.
+__global__ __launch_bounds__(256) void visible_kernel(const fa_ray *rays, int64_t nrays,
+                                                      int samples, int chunk, int nb0, int nb1,
+                                                      int nb2, float o0, float o1, float o2,
+                                                      float r0, float r1, float r2,
+                                                      int32_t *flags) {
+#pragma clang fp contract(off)
+    const int nch = (samples + chunk - 1) / chunk;
+    const int64_t total = nrays * nch;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ri = w / nch;
+        const int c = (int)(w - ri * nch);
+        const fa_ray r = rays[ri];
+        if (!(r.t1 > r.t0)) continue;
+        const float dt = (r.t1 - r.t0) / (float)samples;
+        int last = -1;
+        const int s1 = (c + 1) * chunk < samples ? (c + 1) * chunk : samples;
+        for (int s = c * chunk; s < s1; ++s) {
+            const float ts = ((float)s + 0.5f) * dt;
+            const float tt = r.t0 + ts;
+            const float x = r.origin[0] + tt * r.dir[0];
+            const float y = r.origin[1] + tt * r.dir[1];
+            const float z = r.origin[2] + tt * r.dir[2];
+            float u;
+            const int bx = lookup_axis(x, o0, r0, nb0, u);
+            const int by = lookup_axis(y, o1, r1, nb1, u);
+            const int bz = lookup_axis(z, o2, r2, nb2, u);
+            const int cell = (bx * nb1 + by) * nb2 + bz;
+            if (cell != last) {
+                flags[cell] = 1;
+                last = cell;
+            }
+        }
+    }
+}
+
+__global__ void fill_kernel(int32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_visible(const fa_ray *rays, int64_t nrays, int samples, const int nb[3],
+                          const float origin[3], const float rscale[3], int32_t *flags,
+                          hipStream_t s) {
+    const int64_t ncells = (int64_t)nb[0] * nb[1] * nb[2];
+    const int fgrid = (int)std::min<int64_t>((ncells + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_kernel, dim3(fgrid), dim3(256), 0, s, flags, ncells);
+    const int chunk = 64;
+    const int64_t work = nrays * ((samples + chunk - 1) / chunk);
+    const int grid = (int)std::min<int64_t>((work + 255) / 256, 65536);
+    hipLaunchKernelGGL(visible_kernel, dim3(grid), dim3(256), 0, s, rays, nrays, samples, chunk,
+                       nb[0], nb[1], nb[2], origin[0], origin[1], origin[2], rscale[0],
+                       rscale[1], rscale[2], flags);
+    return hipGetLastError();
+}
 
 hipError_t launch_render(const QueryLaunch &q, const fa_ray *rays, int width, int height,
                          const fa_render_params &p, const float *tf, float *image,
