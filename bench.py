@@ -36,7 +36,6 @@ KERNEL_SOURCES = {
     "adjoint": ["paper_2409_00184_amd/csrc/fa_adjoint.hip",
                 "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "ncp_search": ["paper_2409_00184_amd/csrc/fa_fit.hip",
-                   "paper_2409_00184_amd/csrc/fa_adjoint.hip",
                    "paper_2409_00184_amd/csrc/fa_decode.hip",
                    "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "fit_decode": ["paper_2409_00184_amd/csrc/fa_fit.hip",
@@ -463,11 +462,13 @@ def bench_f2(args):
     for n in (8, 32, 64):
         m = fa.uniform_models(np.full((nb, 3), n), np.full(nb, p))
         dec = torch.empty_like(Y)
-        f_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y), 5, 2, stream)[1]
+        fws = torch.empty(fa.lib.fa_fit_workspace(nb, fa._i32x3((R, R, R)), n),
+                          dtype=torch.uint8, device="cuda")
+        f_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y, workspace=fws), 5, 2, stream)[1]
         e_ms = timed_steps(lambda: fa.model_errors(m, (R, R, R), Y, decoded=dec), 5, 2,
                            stream)[1]
         stages[str(n)] = {"fit_ms": f_ms, "errors_ms": e_ms}
-        del m, dec
+        del m, dec, fws
     vox = nb * R ** 3
     # HBM floor of the four passes over the voxels per candidate: the adjoint
     # reads y, the decode writes f, the residual reads y and f (16 B/voxel)
@@ -618,16 +619,18 @@ def bench_f4(args):
     m = fa.uniform_models(np.full((nb, 3), n_fam), np.full(nb, p))
     out = torch.empty((nb, 4, R, R, R), device="cuda")
     plan = fa.Plan(m, (R, R, R), rows=4, waves=4, grid=1 << 20, store=0)
+    fws = torch.empty(fa.lib.fa_fit_workspace(nb, fa._i32x3((R, R, R)), n_fam),
+                      dtype=torch.uint8, device="cuda")
 
     def step():
-        fa.fit(m, (R, R, R), Y)
+        fa.fit(m, (R, R, R), Y, workspace=fws)
         fa.decode(m, (R, R, R), 15, plan=plan, out=out)
 
     stream = torch.cuda.current_stream()
     graph, _ = fa.capture(step)
     ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
     del graph
-    fit_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y), 5, 2, stream)[1]
+    fit_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y, workspace=fws), 5, 2, stream)[1]
     dec_ms = timed_steps(lambda: fa.decode(m, (R, R, R), 15, plan=plan, out=out), 5, 2,
                          stream)[1]
     step()

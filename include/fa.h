@@ -297,21 +297,28 @@ fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctr
  * Least-squares fit of every micro-model's lattice to samples on its decode
  * grid: the model(NCP, degree) step of Alg. 1 (Sec. 4.2.1).  With B the
  * value map of fa_decode_blocks at `res` (grid u_i = fl32(i / (res - 1))),
- * ctrl = argmin_P |y - B P|_2 = y x_1 B_x^+ x_2 B_y^+ x_3 B_z^+, computed as
- * B^T y (the decode adjoint) followed by a band Cholesky solve with the Gram
- * matrix B_a^T B_a along each axis (factor in FP64, lines solved in FP64,
- * stored FP32).
+ * ctrl = argmin_P |y - B P|_2 = y x_1 B_x^+ x_2 B_y^+ x_3 B_z^+, with each
+ * per-axis pseudo-inverse B_a^+ = (B_a^T B_a)^{-1} B_a^T formed in FP64 (FP64
+ * basis at the FP32 grid positions, band Cholesky of the Gram matrix) and
+ * applied as FP64 contractions; the lattice is rounded to FP32 once.
  *   blocks, knots  device descriptors/knots (FP32 lattices); ncp[a] <= res[a]
  *                  is the caller's to guarantee (a larger ncp makes the Gram
  *                  matrix singular and the lattice non-finite)
  *   samples        device FP32 [nblocks][res0][res1][res2]
  *   ctrl           device FP32, lattice layout; the blocks' lattices are
  *                  overwritten, other elements are left untouched
- * Errors: FA_ERR_INVALID_ARG for null pointers, nblocks <= 0, res < 2;
- * FA_ERR_UNSUPPORTED for res[0] > FA_MAX_RES or res[1], res[2] > 64.
+ *   max_ncp        >= ncp[2] of every block (blocks above it are skipped)
+ *   workspace      device, >= fa_fit_workspace(nblocks, res, max_ncp) bytes,
+ *                  256-B aligned (FP64 intermediate; the call allocates
+ *                  nothing)
+ * Errors: FA_ERR_INVALID_ARG for null pointers, nblocks <= 0, res < 2,
+ * max_ncp < 2, a small or misaligned workspace; FA_ERR_UNSUPPORTED for
+ * res > 64 on any axis or max_ncp > FA_MAX_NCP.
  */
+int64_t fa_fit_workspace(int32_t nblocks, const int32_t res[3], int32_t max_ncp);
 fa_status fa_fit_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
-                        const int32_t res[3], const float *samples, float *ctrl, void *stream);
+                        const int32_t res[3], const float *samples, float *ctrl, int32_t max_ncp,
+                        void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
  * Error of every micro-model against samples on its decode grid (Error(NCP)
@@ -343,7 +350,7 @@ int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t d
  *   samples    device FP32 [nblocks][res0][res1][res2]
  *   workspace  device, >= fa_ncp_search_workspace(...) bytes, 256-B aligned
  * Requires degree + 1 <= ncp_lo <= ncp_hi <= min(res) (FA_ERR_INVALID_ARG
- * otherwise); degree > 3, ncp_hi > FA_MAX_NCP, res[1] or res[2] > 64 give
+ * otherwise); degree > 3, ncp_hi > FA_MAX_NCP or res > 64 on any axis give
  * FA_ERR_UNSUPPORTED.  Asynchronous on `stream`; no allocation.
  */
 fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res[3],

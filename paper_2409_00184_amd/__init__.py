@@ -101,8 +101,10 @@ def _load():
     L.fa_render_rays.restype = ctypes.c_int
     L.fa_render_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32,
                                  vp, vp, vp, vp]
+    L.fa_fit_workspace.restype = i64
+    L.fa_fit_workspace.argtypes = [i32, vp, i32]
     L.fa_fit_blocks.restype = ctypes.c_int
-    L.fa_fit_blocks.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.fa_fit_blocks.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, i64, vp]
     L.fa_model_errors.restype = ctypes.c_int
     L.fa_model_errors.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, vp, vp, vp, i64, vp]
     L.fa_ncp_search_workspace.restype = i64
@@ -377,13 +379,20 @@ def uniform_models(ncp, degree, device="cuda"):
                        np.zeros(nc.value, np.float32), device)
 
 
-def fit(models, res, samples, stream=None):
+def fit(models, res, samples, workspace=None, stream=None):
     """Least-squares lattices (fa_fit_blocks) of samples [nb, *res] float32;
     overwrites models.ctrl (and drops low-precision copies)."""
     assert samples.dtype == torch.float32 and samples.is_contiguous()
     assert samples.numel() == models.nblocks * int(np.prod(res))
+    max_n = int(models.host_desc["ncp"][:, 2].max())
+    need = lib.fa_fit_workspace(models.nblocks, _i32x3(res), max_n)
+    if need < 0:
+        raise FAError("fa_fit_workspace", FA_ERR_INVALID_ARG)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=models.device)
     st = lib.fa_fit_blocks(_ptr(models.desc), models.nblocks, _ptr(models.knots), _i32x3(res),
-                           _ptr(samples), _ptr(models.ctrl), _stream(stream))
+                           _ptr(samples), _ptr(models.ctrl), max_n, _ptr(workspace),
+                           workspace.numel(), _stream(stream))
     _check("fa_fit_blocks", st)
     models.set_ctrl(models.ctrl)
     return models

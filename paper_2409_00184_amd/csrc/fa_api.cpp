@@ -393,15 +393,24 @@ fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctr
 }
 
 
+int64_t fa_fit_workspace(int32_t nblocks, const int32_t res[3], int32_t max_ncp) {
+    if (nblocks <= 0 || !res_ok(res) || max_ncp < 2) return -1;
+    return fit_workspace_bytes(nblocks, res[0], res[1], max_ncp);
+}
+
 fa_status fa_fit_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
-                        const int32_t res[3], const float *samples, float *ctrl, void *stream) {
-    if (!blocks || nblocks <= 0 || !knots || !res_ok(res) || !samples || !ctrl)
+                        const int32_t res[3], const float *samples, float *ctrl, int32_t max_ncp,
+                        void *workspace, int64_t workspace_bytes, void *stream) {
+    if (!blocks || nblocks <= 0 || !knots || !res_ok(res) || !samples || !ctrl || !workspace ||
+        max_ncp < 2)
         return FA_ERR_INVALID_ARG;
-    if (!res_supported(res) || res[1] > 64 || res[2] > 64) return FA_ERR_UNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_adjoint(blocks, nblocks, knots, res[0], res[1], res[2], 1u, samples,
-                                  ctrl, 2, s);
-    if (e == hipSuccess) e = launch_fit_solve(blocks, nblocks, knots, res[0], res[1], res[2], ctrl, s);
+    if (res[0] > 64 || res[1] > 64 || res[2] > 64 || max_ncp > FA_MAX_NCP)
+        return FA_ERR_UNSUPPORTED;
+    if (workspace_bytes < fit_workspace_bytes(nblocks, res[0], res[1], max_ncp) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return FA_ERR_INVALID_ARG;
+    hipError_t e = launch_fit(blocks, nblocks, knots, res[0], res[1], res[2], max_ncp, samples,
+                              static_cast<double *>(workspace), ctrl, (hipStream_t)stream);
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
@@ -427,7 +436,7 @@ namespace {
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct SearchLayout {
-    int64_t desc, knots, ctrl, decoded, total, cstride;
+    int64_t desc, knots, ctrl, decoded, fitws, total, cstride;
 };
 
 SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree,
@@ -439,7 +448,8 @@ SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree
     L.knots = align_up(L.desc + (int64_t)nblocks * (int64_t)sizeof(fa_block), 256);
     L.ctrl = align_up(L.knots + 3 * (int64_t)(ncp_hi + degree + 1) * 4, 256);
     L.decoded = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
-    L.total = align_up(L.decoded + (int64_t)nblocks * vox * 4, 256);
+    L.fitws = align_up(L.decoded + (int64_t)nblocks * vox * 4, 256);
+    L.total = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
     return L;
 }
 
@@ -453,8 +463,8 @@ bool search_args_ok(int32_t nblocks, const int32_t res[3], int32_t degree, int32
 }
 
 bool search_supported(const int32_t res[3], int32_t degree, int32_t ncp_hi) {
-    return degree <= FA_MAX_DEGREE && ncp_hi <= FA_MAX_NCP && res_supported(res) &&
-           res[1] <= 64 && res[2] <= 64;
+    return degree <= FA_MAX_DEGREE && ncp_hi <= FA_MAX_NCP && res[0] <= 64 && res[1] <= 64 &&
+           res[2] <= 64;
 }
 }  // namespace
 
@@ -484,7 +494,8 @@ fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res
     for (int n = ncp_hi; n >= ncp_lo; --n) {
         hipError_t e = launch_candidate(desc, knots, nblocks, n, degree, L.cstride, s);
         if (e != hipSuccess) return FA_ERR_DEVICE;
-        fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, stream);
+        fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, n, w + L.fitws,
+                                     L.total - L.fitws, stream);
         if (st != FA_OK) return st;
         st = fa_model_errors(desc, nblocks, knots, ctrl, FA_F32, res, samples, decoded,
                              errs + 2 * (n - ncp_lo), 2 * (int64_t)ncand, stream);

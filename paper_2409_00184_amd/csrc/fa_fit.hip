@@ -4,21 +4,25 @@
 //
 // The design matrix of a block is the Kronecker product of the per-axis
 // collocation matrices B_a[i][j] = N_j(u_i) on the decode grid, so the
-// least-squares lattice is P = y x_1 B_x^+ x_2 B_y^+ x_3 B_z^+ with
-// B_a^+ = (B_a^T B_a)^{-1} B_a^T.  The B^T part is exactly the decode
-// adjoint (fa_adjoint.hip, value channel); what remains is a solve with the
-// Gram matrix G_a = B_a^T B_a along every axis.  G_a is symmetric positive
-// definite (full column rank when res >= ncp on the uniform grid) and
-// banded with half-bandwidth p (two degree-p B-splines overlap only when
-// their indices differ by at most p), so a band Cholesky factor of at most
-// 64 x 4 entries, built per block in FP64 from the same FP32 basis values
-// the decode uses, serves every line of the axis.
-//
-// solve kernel: one workgroup per block; per axis, the factor is built in
-// LDS, then the lattice lines along that axis are solved in chunks of 256
-// lines staged in LDS in FP64 (one rounding to FP32 per axis pass).
+// least-squares lattice is P = y x_1 X_x x_2 X_y x_3 X_z with the
+// pseudo-inverses X_a = B_a^+ = (B_a^T B_a)^{-1} B_a^T (n_a x R_a).  Each X_a
+// is built in FP64 inside the workgroup that needs it: the basis at the
+// grid points in FP64 (same spans as the decode), the band Gram matrix
+// B_a^T B_a (half-bandwidth p), its band Cholesky factor, and one
+// forward/backward solve per grid point.  Forming X_a first and applying it
+// as a dense contraction keeps the error proportional to the condition
+// number of B_a, where solving the normal equations on B^T y would square
+// it (the collocation matrix of NCP close to R on the uniform grid is
+// badly conditioned).  The contraction runs in FP64 in two kernels:
+//   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (one thread per
+//           (x, y) line, lines staged in LDS, T in a caller workspace),
+//   fit_xy: for each k, P[:, :, k] = X_x T[b][k] X_y^T        (one workgroup
+//           per (block, k), the slice in LDS),
+// and the lattice is rounded to FP32 once.
 // residual kernel: one workgroup per block reduces y - f to (max |r|,
 // sqrt(mean r^2)) in a fixed order (deterministic).
+#include <algorithm>
+
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -26,134 +30,199 @@ namespace fa {
 namespace {
 
 constexpr int kFitThreads = 256;
-constexpr int kFitLines = 256;  // lattice lines per LDS chunk
-constexpr int kFitMaxN = FA_MAX_NCP;
+constexpr int kFitR = 64;  // grid points per axis a fit supports
+constexpr int kFitN = FA_MAX_NCP;
 
-struct FitSmem {
-    double x[kFitMaxN][kFitLines];  // x[j][line]: chunk of lines along the axis
-    double L[kFitMaxN][4];          // band Cholesky factor: L[j][d] = L(j, j - d)
-    double G[kFitMaxN][4];          // band Gram matrix: G[j][d] = G(j, j + d)
-    float N[kMaxRes][4];            // basis at the grid points of the axis
-    int span[kMaxRes];
+// FP64 basis of degree p <= 3 on span s: N[r] = N_{s-p+r,p}(u), triangular
+// form of the de Boor recursion.
+__device__ __forceinline__ void basis64(const float *t, int s, double u, int p, double (&N)[4]) {
+    double left[4] = {0, 0, 0, 0}, right[4] = {0, 0, 0, 0};
+    N[0] = 1.0;
+    N[1] = N[2] = N[3] = 0.0;
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        if (k > p) break;
+        left[k] = u - (double)t[s + 1 - k];
+        right[k] = (double)t[s + k] - u;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < k; ++r) {
+            const double q = N[r] / (right[r + 1] + left[k - r]);
+            N[r] = saved + right[r + 1] * q;
+            saved = left[k - r] * q;
+        }
+        N[k] = saved;
+    }
+}
+
+struct PinvScratch {
+    double N[kFitR][4];
+    int span[kFitR];
+    double G[kFitN][4];  // G[j][d] = G(j, j + d)
+    double L[kFitN][4];  // L[j][d] = L(j, j - d)
 };
 
-__global__ __launch_bounds__(kFitThreads) void fit_solve_kernel(const fa_block *blocks,
-                                                                 int nblocks, const float *knots,
-                                                                 int r0, int r1, int r2,
-                                                                 float *ctrl) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    FitSmem &sm = *reinterpret_cast<FitSmem *>(smem_raw);
+// X = B^+ of one axis (n functions of degree p, knots t, R grid points),
+// written as X[j * sj + i * si] for j < n, i < R.  All threads of the
+// workgroup take part; ends with a barrier.
+__device__ void build_pinv(PinvScratch &w, const float *t, int n, int p, int R, double *X,
+                           int sj, int si) {
     const int tid = threadIdx.x;
-    for (int bi = blockIdx.x; bi < nblocks; bi += gridDim.x) {
-        const fa_block b = blocks[bi];
-        const int n[3] = {b.ncp[0], b.ncp[1], b.ncp[2]};
-        const int R[3] = {r0, r1, r2};
-        const float *tb = knots + b.knot_off;
-        float *P = ctrl + b.ctrl_off;
-        for (int a = 0; a < 3; ++a) {
-            const int na = n[a], p = b.degree[a], Ra = R[a];
-            const float *t = tb + (a >= 1 ? n[0] + b.degree[0] + 1 : 0) +
-                             (a >= 2 ? n[1] + b.degree[1] + 1 : 0);
-            // basis of the axis at the decode grid (the decode's FP32 values)
-            for (int i = tid; i < Ra; i += kFitThreads) {
-                const float u = grid_pos(i, Ra);
-                const int s = span_search(na, p, t, u);
-                float Nv[4], Dv[4];
-                basis_ders_rt(t, s, u, p, Nv, Dv);
-                sm.span[i] = s;
+    for (int i = tid; i < R; i += kFitThreads) {
+        const float uf = grid_pos(i, R);
+        const int s = span_search(n, p, t, uf);
+        double Nv[4];
+        basis64(t, s, (double)uf, p, Nv);
+        w.span[i] = s;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sm.N[i][r] = Nv[r];
+        for (int r = 0; r < 4; ++r) w.N[i][r] = Nv[r];
+    }
+    __syncthreads();
+    for (int e = tid; e < n * 4; e += kFitThreads) {
+        const int j = e >> 2, d = e & 3;
+        double g = 0.0;
+        if (d <= p)
+            for (int i = 0; i < R; ++i) {
+                const int r = j - (w.span[i] - p);
+                if (r >= 0 && r + d <= p) g += w.N[i][r] * w.N[i][r + d];
             }
-            __syncthreads();
-            // band Gram matrix G(j, j+d) = sum_i N_j(u_i) N_{j+d}(u_i), FP64
-            for (int e = tid; e < na * 4; e += kFitThreads) {
-                const int j = e >> 2, d = e & 3;
-                double g = 0.0;
-                if (d <= p) {
-                    for (int i = 0; i < Ra; ++i) {
-                        const int s0 = sm.span[i] - p;  // first non-zero function at u_i
-                        const int r = j - s0;
-                        if (r >= 0 && r + d <= p) g += (double)sm.N[i][r] * (double)sm.N[i][r + d];
-                    }
+        w.G[j][d] = g;
+    }
+    __syncthreads();
+    if (tid == 0) {  // band Cholesky G = L L^T
+        for (int j = 0; j < n; ++j) {
+            for (int d = p; d >= 1; --d) {
+                const int k = j - d;
+                if (k < 0) {
+                    w.L[j][d] = 0.0;
+                    continue;
                 }
-                sm.G[j][d] = g;
+                double v = w.G[k][d];
+                for (int m = d + 1; m <= p; ++m)
+                    if (j - m >= 0) v -= w.L[j][m] * w.L[k][m - d];
+                w.L[j][d] = v / w.L[k][0];
             }
-            __syncthreads();
-            // band Cholesky G = L L^T (sequential, at most 64 x 4 entries)
-            if (tid == 0) {
-                for (int j = 0; j < na; ++j) {
-                    for (int d = p; d >= 1; --d) {  // L(j, j-d)
-                        const int k = j - d;
-                        if (k < 0) {
-                            sm.L[j][d] = 0.0;
-                            continue;
-                        }
-                        double v = sm.G[k][d];  // G(k, j) = G(j, k)
-                        for (int m = d + 1; m <= p; ++m)  // sum_c L(j, c) L(k, c), c = j - m
-                            if (j - m >= 0) v -= sm.L[j][m] * sm.L[k][m - d];
-                        sm.L[j][d] = v / sm.L[k][0];
-                    }
-                    double v = sm.G[j][0];
-                    for (int d = 1; d <= p; ++d) v -= sm.L[j][d] * sm.L[j][d];
-                    sm.L[j][0] = sqrt(v);
-                }
-            }
-            __syncthreads();
-            // lines along axis a: element j of line l sits at base(l) + j * stride
-            const int64_t nyz = (int64_t)n[1] * n[2];
-            const int64_t nlines = (int64_t)n[0] * n[1] * n[2] / na;
-            const int64_t stride = a == 0 ? nyz : (a == 1 ? n[2] : 1);
-            auto base = [&](int64_t l) -> int64_t {
-                if (a == 0) return l;
-                if (a == 1) return (l / n[2]) * nyz + (l % n[2]);
-                return l * n[2];
-            };
-            for (int64_t l0 = 0; l0 < nlines; l0 += kFitLines) {
-                const int cl = (int)(nlines - l0 < kFitLines ? nlines - l0 : kFitLines);
-                // load (global addresses contiguous across threads)
-                for (int e = tid; e < cl * na; e += kFitThreads) {
-                    int li, j;
-                    if (a == 2) {
-                        li = e / na;
-                        j = e - li * na;
-                    } else {
-                        j = e / cl;
-                        li = e - j * cl;
-                    }
-                    sm.x[j][li] = (double)P[base(l0 + li) + j * stride];
-                }
-                __syncthreads();
-                if (tid < cl) {
-                    // forward: L z = rhs
-                    for (int j = 0; j < na; ++j) {
-                        double v = sm.x[j][tid];
-                        for (int d = 1; d <= p; ++d)
-                            if (j - d >= 0) v -= sm.L[j][d] * sm.x[j - d][tid];
-                        sm.x[j][tid] = v / sm.L[j][0];
-                    }
-                    // backward: L^T x = z
-                    for (int j = na - 1; j >= 0; --j) {
-                        double v = sm.x[j][tid];
-                        for (int d = 1; d <= p; ++d)
-                            if (j + d < na) v -= sm.L[j + d][d] * sm.x[j + d][tid];
-                        sm.x[j][tid] = v / sm.L[j][0];
-                    }
-                }
-                __syncthreads();
-                for (int e = tid; e < cl * na; e += kFitThreads) {
-                    int li, j;
-                    if (a == 2) {
-                        li = e / na;
-                        j = e - li * na;
-                    } else {
-                        j = e / cl;
-                        li = e - j * cl;
-                    }
-                    P[base(l0 + li) + j * stride] = (float)sm.x[j][li];
-                }
-                __syncthreads();
+            double v = w.G[j][0];
+            for (int d = 1; d <= p; ++d) v -= w.L[j][d] * w.L[j][d];
+            w.L[j][0] = sqrt(v);
+        }
+    }
+    __syncthreads();
+    // column i of X solves G x = B[i, :]^T (non-zero at s_i - p .. s_i)
+    for (int i = tid; i < R; i += kFitThreads) {
+        const int j0 = w.span[i] - p;
+        for (int j = 0; j < n; ++j) {  // forward: L z = rhs
+            double v = (j >= j0 && j <= j0 + p) ? w.N[i][j - j0] : 0.0;
+            if (j > j0)
+                for (int d = 1; d <= p; ++d)
+                    if (j - d >= j0) v -= w.L[j][d] * X[(j - d) * sj + i * si];
+            X[j * sj + i * si] = j >= j0 ? v / w.L[j][0] : 0.0;
+        }
+        for (int j = n - 1; j >= 0; --j) {  // backward: L^T x = z
+            double v = X[j * sj + i * si];
+            for (int d = 1; d <= p; ++d)
+                if (j + d < n) v -= w.L[j + d][d] * X[(j + d) * sj + i * si];
+            X[j * sj + i * si] = v / w.L[j][0];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ const float *axis_knots(const float *knots, const fa_block &b, int a) {
+    const float *t = knots + b.knot_off;
+    if (a >= 1) t += b.ncp[0] + b.degree[0] + 1;
+    if (a >= 2) t += b.ncp[1] + b.degree[1] + 1;
+    return t;
+}
+
+struct FitZSmem {
+    double X[kFitN][kFitR];                 // X_z[k][z]
+    float ys[kFitThreads][kFitR + 1];       // staged lines (padded)
+    PinvScratch w;
+};
+
+// T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y, one thread per line
+__global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
+                                                            const float *knots, int r0, int r1,
+                                                            int r2, int max_n, const float *y,
+                                                            double *T) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    FitZSmem &sm = *reinterpret_cast<FitZSmem *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int64_t lines = (int64_t)r0 * r1;
+    const int chunks = (int)((lines + kFitThreads - 1) / kFitThreads);
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * chunks; item += gridDim.x) {
+        const int bi = (int)(item / chunks);
+        const int64_t l0 = (item - (int64_t)bi * chunks) * kFitThreads;
+        const fa_block b = blocks[bi];
+        const int nz = b.ncp[2], p = b.degree[2];
+        if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
+        build_pinv(sm.w, axis_knots(knots, b, 2), nz, p, r2, &sm.X[0][0], kFitR, 1);
+        const int cl = (int)(lines - l0 < kFitThreads ? lines - l0 : kFitThreads);
+        const float *yb = y + ((int64_t)bi * lines + l0) * r2;
+        for (int e = tid; e < cl * r2; e += kFitThreads) {
+            const int li = e / r2;
+            sm.ys[li][e - li * r2] = yb[e];
+        }
+        __syncthreads();
+        if (tid < cl) {
+            double *Tb = T + (int64_t)bi * max_n * lines + l0 + tid;
+            for (int k = 0; k < nz; ++k) {
+                double acc = 0.0;
+                for (int z = 0; z < r2; ++z) acc += sm.X[k][z] * (double)sm.ys[tid][z];
+                Tb[(int64_t)k * lines] = acc;
             }
         }
+        __syncthreads();
+    }
+}
+
+struct FitXYSmem {
+    double Xx[kFitN][kFitR];      // X_x[i][x]
+    double XyT[kFitR][kFitN + 1]; // X_y transposed: XyT[y][j]
+    double S[kFitR][kFitR];       // slice T[b][k] as [x][y]
+    double U[kFitN][kFitR];       // X_x S
+    PinvScratch w;
+};
+
+__global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
+                                                             const float *knots, int r0, int r1,
+                                                             int max_n, const double *T,
+                                                             float *ctrl) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    FitXYSmem &sm = *reinterpret_cast<FitXYSmem *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int64_t lines = (int64_t)r0 * r1;
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * max_n; item += gridDim.x) {
+        const int bi = (int)(item / max_n);
+        const int k = (int)(item - (int64_t)bi * max_n);
+        const fa_block b = blocks[bi];
+        const int nx = b.ncp[0], ny = b.ncp[1], nz = b.ncp[2];
+        if (k >= nz || nz > max_n) continue;
+        build_pinv(sm.w, axis_knots(knots, b, 0), nx, b.degree[0], r0, &sm.Xx[0][0], kFitR, 1);
+        build_pinv(sm.w, axis_knots(knots, b, 1), ny, b.degree[1], r1, &sm.XyT[0][0], 1,
+                   kFitN + 1);
+        const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
+        for (int e = tid; e < (int)lines; e += kFitThreads) {
+            const int x = e / r1;
+            sm.S[x][e - x * r1] = Tk[e];
+        }
+        __syncthreads();
+        for (int e = tid; e < nx * r1; e += kFitThreads) {  // U = X_x S
+            const int i = e / r1, yy = e - i * r1;
+            double acc = 0.0;
+            for (int x = 0; x < r0; ++x) acc += sm.Xx[i][x] * sm.S[x][yy];
+            sm.U[i][yy] = acc;
+        }
+        __syncthreads();
+        float *Pb = ctrl + b.ctrl_off;
+        for (int e = tid; e < nx * ny; e += kFitThreads) {  // P[:, :, k] = U X_y^T
+            const int i = e / ny, j = e - i * ny;
+            double acc = 0.0;
+            for (int yy = 0; yy < r1; ++yy) acc += sm.U[i][yy] * sm.XyT[yy][j];
+            Pb[((int64_t)i * ny + j) * nz + k] = (float)acc;
+        }
+        __syncthreads();
     }
 }
 
@@ -231,15 +300,30 @@ __global__ void candidate_kernel(fa_block *desc, float *knots, int nblocks, int 
 
 }  // namespace
 
-hipError_t launch_fit_solve(const fa_block *blocks, int nblocks, const float *knots, int rx,
-                            int ry, int rz, float *ctrl, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&fit_solve_kernel),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(FitSmem));
+int64_t fit_workspace_bytes(int nblocks, int rx, int ry, int max_n) {
+    return (int64_t)nblocks * max_n * rx * ry * (int64_t)sizeof(double);
+}
+
+hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,
+                      int rz, int max_n, const float *samples, double *T, float *ctrl,
+                      hipStream_t s) {
+    static const hipError_t attr = [] {
+        hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_z_kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)sizeof(FitZSmem));
+        hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_xy_kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)sizeof(FitXYSmem));
+        return e1 != hipSuccess ? e1 : e2;
+    }();
     if (attr != hipSuccess) return attr;
-    const int grid = nblocks < 65536 ? nblocks : 65536;
-    hipLaunchKernelGGL(fit_solve_kernel, dim3(grid), dim3(kFitThreads), sizeof(FitSmem), s,
-                       blocks, nblocks, knots, rx, ry, rz, ctrl);
+    const int64_t chunks = ((int64_t)rx * ry + kFitThreads - 1) / kFitThreads;
+    const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
+    hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
+                       nblocks, knots, rx, ry, rz, max_n, samples, T);
+    const int gxy = (int)std::min<int64_t>((int64_t)nblocks * max_n, 65536);
+    hipLaunchKernelGGL(fit_xy_kernel, dim3(gxy), dim3(kFitThreads), sizeof(FitXYSmem), s, blocks,
+                       nblocks, knots, rx, ry, max_n, T, ctrl);
     return hipGetLastError();
 }
 

@@ -70,8 +70,10 @@ hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knot
                           int ry, int rz, uint32_t mask, const float *g, float *G, int it,
                           hipStream_t s);
 
-hipError_t launch_fit_solve(const fa_block *blocks, int nblocks, const float *knots, int rx,
-                            int ry, int rz, float *ctrl, hipStream_t s);
+int64_t fit_workspace_bytes(int nblocks, int rx, int ry, int max_n);
+hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,
+                      int rz, int max_n, const float *samples, double *T, float *ctrl,
+                      hipStream_t s);
 hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblocks, float *errs,
                            int64_t stride, hipStream_t s);
 hipError_t launch_candidate(fa_block *desc, float *knots, int nblocks, int n, int p,

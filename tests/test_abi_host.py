@@ -275,6 +275,19 @@ def test_search_arguments_rejected_without_launch(fa):
     big = fa._i32x3((80, 80, 80))
     assert fa.lib.fa_ncp_search(vp, 4, big, 3, 5, 70, vp, ctypes.c_void_p(256),
                                 fa.lib.fa_ncp_search_workspace(4, big, 3, 70), None) == 2
-    assert fa.lib.fa_fit_blocks(vp, 1, vp, fa._i32x3((64, 65, 64)), vp, vp, None) == 2
-    assert fa.lib.fa_fit_blocks(None, 1, vp, r, vp, vp, None) == 1
+    wide = fa._i32x3((80, 16, 16))
+    assert fa.lib.fa_ncp_search(vp, 4, wide, 3, 5, 16, vp, ctypes.c_void_p(256),
+                                fa.lib.fa_ncp_search_workspace(4, wide, 3, 16), None) == 2
+    fws = fa.lib.fa_fit_workspace(4, r, 16)
+    assert fws == 4 * 16 * 16 * 16 * 8
+    assert fa.lib.fa_fit_blocks(vp, 1, vp, fa._i32x3((64, 65, 64)), vp, vp, 16,
+                                ctypes.c_void_p(256), 1 << 30, None) == 2
+    assert fa.lib.fa_fit_blocks(vp, 1, vp, r, vp, vp, 65, ctypes.c_void_p(256), 1 << 30,
+                                None) == 2
+    assert fa.lib.fa_fit_blocks(None, 1, vp, r, vp, vp, 16, ctypes.c_void_p(256), fws,
+                                None) == 1
+    assert fa.lib.fa_fit_blocks(vp, 4, vp, r, vp, vp, 16, ctypes.c_void_p(256), fws - 1,
+                                None) == 1
+    assert fa.lib.fa_fit_blocks(vp, 4, vp, r, vp, vp, 16, ctypes.c_void_p(264), fws,
+                                None) == 1
     assert fa.lib.fa_model_errors(vp, 1, vp, vp, 0, r, vp, vp, vp, 1, None) == 1
