@@ -824,6 +824,25 @@ def probe(args):
         gin = torch.randn((b.nblocks, 1) + res, device="cuda")
         G = torch.empty_like(m.ctrl)
         run = lambda: fa.decode_backward(m, res, gin, 1, grad_ctrl=G)
+    elif w == "f1":
+        b = fi.config_c3_blocks()
+        m = fa.MicroModels.from_batch(b)
+        rays = torch.as_tensor(fi.render_rays(3, 1920, 1080), device="cuda")
+        tf = torch.as_tensor(fi.transfer_function(4), device="cuda")
+        boc = torch.as_tensor(fi.identity_cells(4096), device="cuda")
+        img = torch.empty((1080, 1920, 4), device="cuda")
+        run = lambda: fa.render(m, rays, 1920, 1080, tf, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc,
+                                512, opacity_max=2.0, tf_range=(-4.0, 4.0), out=img,
+                                light=(0.0, 0.6, 0.8), ka=0.3, kd=0.6, ks=0.3, shininess=16.0)
+    elif w == "f2":
+        import numpy as np
+        Y = torch.as_tensor(fi.turbulence_cube(fi.rng(12), 64, 64)).cuda().contiguous()
+        m = fa.uniform_models(np.full((64, 3), 32), np.full(64, 3))
+        fws = torch.empty(fa.lib.fa_fit_workspace(64, fa._i32x3(res), 32), dtype=torch.uint8,
+                          device="cuda")
+        dec = torch.empty_like(Y)
+        run = lambda: (fa.fit(m, res, Y, workspace=fws),
+                       fa.model_errors(m, res, Y, decoded=dec))
     elif w == "c5":
         b = fi.config_c5()
         m = fa.MicroModels.from_batch(b)

@@ -13,9 +13,11 @@
 // as a dense contraction keeps the error proportional to the condition
 // number of B_a, where solving the normal equations on B^T y would square
 // it (the collocation matrix of NCP close to R on the uniform grid is
-// badly conditioned).  The contraction runs in FP64 in two kernels:
+// badly conditioned).  Three kernels, FP64 throughout:
+//   fit_pinv: X_a of every (block, axis), one workgroup each, into the
+//           caller's workspace,
 //   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (one thread per
-//           (x, y) line, lines staged in LDS, T in a caller workspace),
+//           (x, y) line, lines staged in LDS, T in the workspace),
 //   fit_xy: for each k, P[:, :, k] = X_x T[b][k] X_y^T        (one workgroup
 //           per (block, k), the slice in LDS),
 // and the lattice is rounded to FP32 once.
@@ -135,17 +137,42 @@ __device__ __forceinline__ const float *axis_knots(const float *knots, const fa_
     return t;
 }
 
+constexpr int64_t kPinvStride = (int64_t)kFitN * kFitR;  // doubles per (block, axis)
+
+struct PinvSmem {
+    double X[kFitN][kFitR];
+    PinvScratch w;
+};
+
+// Xg[(b * 3 + a) * kPinvStride + j * kFitR + i] = X_a[j][i]
+__global__ __launch_bounds__(kFitThreads) void fit_pinv_kernel(const fa_block *blocks,
+                                                               int nblocks, const float *knots,
+                                                               int r0, int r1, int r2,
+                                                               double *Xg) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    PinvSmem &sm = *reinterpret_cast<PinvSmem *>(smem_raw);
+    const int R[3] = {r0, r1, r2};
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * 3; item += gridDim.x) {
+        const int bi = (int)(item / 3), a = (int)(item - (int64_t)bi * 3);
+        const fa_block b = blocks[bi];
+        const int n = b.ncp[a];
+        build_pinv(sm.w, axis_knots(knots, b, a), n, b.degree[a], R[a], &sm.X[0][0], kFitR, 1);
+        double *dst = Xg + item * kPinvStride;
+        for (int e = threadIdx.x; e < n * kFitR; e += kFitThreads) dst[e] = (&sm.X[0][0])[e];
+        __syncthreads();
+    }
+}
+
 struct FitZSmem {
     double X[kFitN][kFitR];                 // X_z[k][z]
     float ys[kFitThreads][kFitR + 1];       // staged lines (padded)
-    PinvScratch w;
 };
 
 // T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y, one thread per line
 __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
                                                             const float *knots, int r0, int r1,
                                                             int r2, int max_n, const float *y,
-                                                            double *T) {
+                                                            const double *Xg, double *T) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitZSmem &sm = *reinterpret_cast<FitZSmem *>(smem_raw);
     const int tid = threadIdx.x;
@@ -155,9 +182,10 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
         const int bi = (int)(item / chunks);
         const int64_t l0 = (item - (int64_t)bi * chunks) * kFitThreads;
         const fa_block b = blocks[bi];
-        const int nz = b.ncp[2], p = b.degree[2];
+        const int nz = b.ncp[2];
         if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
-        build_pinv(sm.w, axis_knots(knots, b, 2), nz, p, r2, &sm.X[0][0], kFitR, 1);
+        const double *Xz = Xg + ((int64_t)bi * 3 + 2) * kPinvStride;
+        for (int e = tid; e < nz * kFitR; e += kFitThreads) (&sm.X[0][0])[e] = Xz[e];
         const int cl = (int)(lines - l0 < kFitThreads ? lines - l0 : kFitThreads);
         const float *yb = y + ((int64_t)bi * lines + l0) * r2;
         for (int e = tid; e < cl * r2; e += kFitThreads) {
@@ -182,13 +210,12 @@ struct FitXYSmem {
     double XyT[kFitR][kFitN + 1]; // X_y transposed: XyT[y][j]
     double S[kFitR][kFitR];       // slice T[b][k] as [x][y]
     double U[kFitN][kFitR];       // X_x S
-    PinvScratch w;
 };
 
 __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int r0, int r1,
-                                                             int max_n, const double *T,
-                                                             float *ctrl) {
+                                                             int max_n, const double *Xg,
+                                                             const double *T, float *ctrl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitXYSmem &sm = *reinterpret_cast<FitXYSmem *>(smem_raw);
     const int tid = threadIdx.x;
@@ -199,9 +226,13 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
         const fa_block b = blocks[bi];
         const int nx = b.ncp[0], ny = b.ncp[1], nz = b.ncp[2];
         if (k >= nz || nz > max_n) continue;
-        build_pinv(sm.w, axis_knots(knots, b, 0), nx, b.degree[0], r0, &sm.Xx[0][0], kFitR, 1);
-        build_pinv(sm.w, axis_knots(knots, b, 1), ny, b.degree[1], r1, &sm.XyT[0][0], 1,
-                   kFitN + 1);
+        const double *Xx = Xg + (int64_t)bi * 3 * kPinvStride;
+        const double *Xy = Xx + kPinvStride;
+        for (int e = tid; e < nx * kFitR; e += kFitThreads) (&sm.Xx[0][0])[e] = Xx[e];
+        for (int e = tid; e < ny * kFitR; e += kFitThreads) {
+            const int j = e / kFitR;
+            sm.XyT[e - j * kFitR][j] = Xy[e];
+        }
         const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
         for (int e = tid; e < (int)lines; e += kFitThreads) {
             const int x = e / r1;
@@ -301,7 +332,8 @@ __global__ void candidate_kernel(fa_block *desc, float *knots, int nblocks, int 
 }  // namespace
 
 int64_t fit_workspace_bytes(int nblocks, int rx, int ry, int max_n) {
-    return (int64_t)nblocks * max_n * rx * ry * (int64_t)sizeof(double);
+    return ((int64_t)nblocks * max_n * rx * ry + (int64_t)nblocks * 3 * kPinvStride) *
+           (int64_t)sizeof(double);
 }
 
 hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,
@@ -314,16 +346,23 @@ hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, i
         hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_xy_kernel),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)sizeof(FitXYSmem));
-        return e1 != hipSuccess ? e1 : e2;
+        hipError_t e3 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_pinv_kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)sizeof(PinvSmem));
+        return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
     }();
     if (attr != hipSuccess) return attr;
+    double *Xg = T + (int64_t)nblocks * max_n * rx * ry;
+    const int gp = (int)std::min<int64_t>((int64_t)nblocks * 3, 65536);
+    hipLaunchKernelGGL(fit_pinv_kernel, dim3(gp), dim3(kFitThreads), sizeof(PinvSmem), s, blocks,
+                       nblocks, knots, rx, ry, rz, Xg);
     const int64_t chunks = ((int64_t)rx * ry + kFitThreads - 1) / kFitThreads;
     const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
     hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
-                       nblocks, knots, rx, ry, rz, max_n, samples, T);
+                       nblocks, knots, rx, ry, rz, max_n, samples, Xg, T);
     const int gxy = (int)std::min<int64_t>((int64_t)nblocks * max_n, 65536);
     hipLaunchKernelGGL(fit_xy_kernel, dim3(gxy), dim3(kFitThreads), sizeof(FitXYSmem), s, blocks,
-                       nblocks, knots, rx, ry, max_n, T, ctrl);
+                       nblocks, knots, rx, ry, max_n, Xg, T, ctrl);
     return hipGetLastError();
 }
 

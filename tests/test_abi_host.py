@@ -279,7 +279,7 @@ def test_search_arguments_rejected_without_launch(fa):
     assert fa.lib.fa_ncp_search(vp, 4, wide, 3, 5, 16, vp, ctypes.c_void_p(256),
                                 fa.lib.fa_ncp_search_workspace(4, wide, 3, 16), None) == 2
     fws = fa.lib.fa_fit_workspace(4, r, 16)
-    assert fws == 4 * 16 * 16 * 16 * 8
+    assert fws == (4 * 16 * 16 * 16 + 4 * 3 * 64 * 64) * 8  # T slices + per-axis pseudo-inverses
     assert fa.lib.fa_fit_blocks(vp, 1, vp, fa._i32x3((64, 65, 64)), vp, vp, 16,
                                 ctypes.c_void_p(256), 1 << 30, None) == 2
     assert fa.lib.fa_fit_blocks(vp, 1, vp, r, vp, vp, 65, ctypes.c_void_p(256), 1 << 30,
