@@ -79,6 +79,24 @@ hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblo
 hipError_t launch_candidate(fa_block *desc, float *knots, int nblocks, int n, int p,
                             int64_t cstride, hipStream_t s);
 
+// One block of a staging gather: its slot in the mapped host cache, where
+// its knots and lattice go in the device batch, and its descriptor.
+struct StageEntry {
+    int64_t slot_off;  // floats from the start of the slots
+    int64_t kdst;      // knot destination (floats)
+    int64_t cdst;      // lattice destination (floats, multiple of 64)
+    int64_t cl;        // lattice floats
+    int32_t kl;        // knot floats
+    int32_t koff;      // lattice offset inside the slot (floats, multiple of 4)
+    int32_t dst;       // descriptor index in the batch
+    int32_t pad;
+    fa_block desc;
+};
+
+hipError_t launch_stage_gather(const StageEntry *table, int n, const float *slots,
+                               fa_block *dev_blocks, float *dev_knots, float *dev_ctrl,
+                               hipStream_t s);
+
 hipError_t launch_quantize(fa_block *blocks, int nblocks, const float *ctrl, int dtype,
                            void *out, hipStream_t s);
 

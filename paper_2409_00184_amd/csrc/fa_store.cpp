@@ -8,13 +8,18 @@
 // 1), and the NCP^3 FP32 control points [x][y][z], so its size is
 // 1 + ((NCP + degree) * 3 + NCP^3) * 4 bytes and NCP follows from it.
 //
-// Cache: a fixed number of host slots (page-locked when asked for, so the
-// copies to the GPU are DMA transfers), least-recently-used replacement,
-// a hit refreshing the block's recency.  Staging copies the requested
-// blocks, slot by slot, into a packed device batch (descriptors, knots,
-// lattices at 64-element offsets) with asynchronous copies on the caller's
-// stream; an event per slot keeps a slot from being refilled while a copy
-// from it may still be in flight.
+// Cache: a fixed number of host slots (page-locked and mapped into the GPU's
+// address space when asked for), least-recently-used replacement, a hit
+// refreshing the block's recency.  Staging builds a table of (slot, knot and
+// lattice destinations, descriptor) entries in mapped host memory and
+// launches one gather kernel that reads the slots directly over the host
+// link and writes the packed device batch (descriptors, knots, lattices at
+// 64-element offsets): one launch per call instead of two copies per block.
+// A slot is never refilled while a gather that reads it may still run: a
+// call waits for the previous call's gather before touching the cache, and
+// within a call the gather is launched (and waited for) before a batch
+// reaches the cache's size, since only then could a refill hit one of its
+// slots.
 #include <hip/hip_runtime.h>
 
 #include <fcntl.h>
@@ -28,6 +33,7 @@
 #include <vector>
 
 #include "../../include/fa.h"
+#include "fa_internal.hpp"
 
 namespace {
 
@@ -59,6 +65,7 @@ bool read_at(int fd, void *dst, int64_t n, int64_t off) {
 }
 
 int64_t align64(int64_t v) { return (v + 63) / 64 * 64; }
+int64_t knot_span(int n, int p) { return (3 * (int64_t)(n + p + 1) + 3) / 4 * 4; }
 
 }  // namespace
 
@@ -69,17 +76,17 @@ struct fa_store {
     std::vector<int32_t> ncp, deg;
     int32_t capacity = 0;
     bool pinned = false;
-    int64_t slot_floats = 0;  // 3 (n + p + 1) + n^3 of the largest record
+    int64_t slot_floats = 0;  // knots (padded to 4) + n^3 of the largest record
     float *slots = nullptr;
+    const float *slots_dev = nullptr;  // device view of the mapped slots
     std::vector<char> raw;  // one record as read
     std::vector<int32_t> slot_of_block, block_of_slot;
     std::list<int32_t> lru;  // slots, most recently used first
     std::vector<std::list<int32_t>::iterator> where;
-    std::vector<hipEvent_t> ev;
-    std::vector<char> ev_live;
-    fa_block *desc_stage = nullptr;  // host descriptors of one staging call
-    hipEvent_t desc_ev = nullptr;
-    bool desc_live = false;
+    fa::StageEntry *table = nullptr;  // mapped host table of one gather
+    const fa::StageEntry *table_dev = nullptr;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_live = false;
     fa_store_stats stats{};
 };
 
@@ -103,23 +110,20 @@ int32_t fetch_one(fa_store *s, int32_t b) {
         s->lru.splice(s->lru.begin(), s->lru, s->where[slot]);
         s->slot_of_block[s->block_of_slot[slot]] = -1;
         s->stats.evictions++;
-        if (s->ev_live[slot]) {  // a copy from this slot may still be running
-            hipEventSynchronize(s->ev[slot]);
-            s->ev_live[slot] = 0;
-        }
     }
     const int n = s->ncp[b], p = s->deg[b];
     if (!read_at(s->fd, s->raw.data(), s->size[b], s->off[b])) return -1;
     s->stats.bytes_read += s->size[b];
     float *dst = s->slots + (int64_t)slot * s->slot_floats;
     const char *src = s->raw.data() + 1;
+    float *base = dst;
     for (int a = 0; a < 3; ++a) {
         std::memcpy(dst, src, (size_t)(n + p) * 4);
         dst[n + p] = 1.0f;  // the implicit last knot
         dst += n + p + 1;
         src += (size_t)(n + p) * 4;
     }
-    std::memcpy(dst, src, (size_t)n * n * n * 4);
+    std::memcpy(base + knot_span(n, p), src, (size_t)n * n * n * 4);
     s->slot_of_block[b] = slot;
     s->block_of_slot[slot] = b;
     return slot;
@@ -202,35 +206,32 @@ fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, 
         if (p < 1 || n < 0) return fail(FA_ERR_INVALID_ARG);
         s->ncp[b] = n;
         s->deg[b] = p;
-        s->slot_floats = std::max<int64_t>(s->slot_floats, 3 * (n + p + 1) + (int64_t)n * n * n);
+        s->slot_floats = std::max<int64_t>(s->slot_floats, knot_span(n, p) + (int64_t)n * n * n);
         maxsz = std::max(maxsz, s->size[b]);
     }
     s->capacity = cache_blocks;
     s->raw.resize((size_t)maxsz);
+    s->slot_floats = (s->slot_floats + 3) / 4 * 4;  // 16-byte aligned slots
     const size_t bytes = (size_t)s->capacity * (size_t)s->slot_floats * 4;
     s->pinned = (flags & FA_STORE_PINNED) != 0;
     if (s->pinned) {
-        void *p = nullptr;
-        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess)
-            return fail(FA_ERR_DEVICE);
+        void *p = nullptr, *d = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocMapped) != hipSuccess) return fail(FA_ERR_DEVICE);
         s->slots = static_cast<float *>(p);
-        if (hipHostMalloc(&p, (size_t)s->nblocks * sizeof(fa_block), hipHostMallocDefault) !=
+        if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) return fail(FA_ERR_DEVICE);
+        s->slots_dev = static_cast<const float *>(d);
+        if (hipHostMalloc(&p, (size_t)s->capacity * sizeof(fa::StageEntry), hipHostMallocMapped) !=
             hipSuccess)
             return fail(FA_ERR_DEVICE);
-        s->desc_stage = static_cast<fa_block *>(p);
-        s->ev.assign(s->capacity, nullptr);
-        for (auto &e : s->ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-                return fail(FA_ERR_DEVICE);
-        if (hipEventCreateWithFlags(&s->desc_ev, hipEventDisableTiming) != hipSuccess)
+        s->table = static_cast<fa::StageEntry *>(p);
+        if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) return fail(FA_ERR_DEVICE);
+        s->table_dev = static_cast<const fa::StageEntry *>(d);
+        if (hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming) != hipSuccess)
             return fail(FA_ERR_DEVICE);
     } else {
         s->slots = static_cast<float *>(std::malloc(bytes));
-        s->desc_stage = static_cast<fa_block *>(std::malloc((size_t)s->nblocks * sizeof(fa_block)));
-        if (!s->slots || !s->desc_stage) return fail(FA_ERR_DEVICE);
-        s->ev.assign(s->capacity, nullptr);
+        if (!s->slots) return fail(FA_ERR_DEVICE);
     }
-    s->ev_live.assign(s->capacity, 0);
     s->slot_of_block.assign(s->nblocks, -1);
     s->block_of_slot.assign(s->capacity, -1);
     s->where.resize(s->capacity);
@@ -241,20 +242,14 @@ fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, 
 fa_status fa_store_close(fa_store *s) {
     if (!s) return FA_ERR_INVALID_ARG;
     if (s->pinned) {
-        for (size_t i = 0; i < s->ev.size(); ++i)
-            if (s->ev[i]) {
-                if (s->ev_live[i]) hipEventSynchronize(s->ev[i]);
-                hipEventDestroy(s->ev[i]);
-            }
-        if (s->desc_ev) {
-            if (s->desc_live) hipEventSynchronize(s->desc_ev);
-            hipEventDestroy(s->desc_ev);
+        if (s->stage_ev) {
+            if (s->stage_live) hipEventSynchronize(s->stage_ev);
+            hipEventDestroy(s->stage_ev);
         }
         if (s->slots) hipHostFree(s->slots);
-        if (s->desc_stage) hipHostFree(s->desc_stage);
+        if (s->table) hipHostFree(s->table);
     } else {
         std::free(s->slots);
-        std::free(s->desc_stage);
     }
     if (s->fd >= 0) close(s->fd);
     delete s;
@@ -293,7 +288,7 @@ fa_status fa_store_slot(const fa_store *s, int32_t slot, int32_t *block, const f
     const float *base = s->slots + (int64_t)slot * s->slot_floats;
     if (block) *block = b;
     if (knots) *knots = base;
-    if (ctrl) *ctrl = base + 3 * (s->ncp[b] + s->deg[b] + 1);
+    if (ctrl) *ctrl = base + knot_span(s->ncp[b], s->deg[b]);
     return FA_OK;
 }
 
@@ -312,26 +307,32 @@ fa_status fa_store_stage(fa_store *s, const int32_t *ids, int32_t n, fa_block *d
     }
     if (kneed > knot_capacity || align64(cneed) > ctrl_capacity) return FA_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    if (s->desc_live) {  // the previous call's descriptor copy reads desc_stage
-        if (hipEventSynchronize(s->desc_ev) != hipSuccess) return FA_ERR_DEVICE;
-        s->desc_live = false;
+    if (s->stage_live) {  // the previous gather reads the table and its slots
+        if (hipEventSynchronize(s->stage_ev) != hipSuccess) return FA_ERR_DEVICE;
+        s->stage_live = false;
     }
+    int32_t batch = 0;
+    auto flush = [&](bool wait) -> bool {
+        if (batch == 0) return true;
+        if (fa::launch_stage_gather(s->table_dev, batch, s->slots_dev, dev_blocks, dev_knots,
+                                    dev_ctrl, st) != hipSuccess ||
+            hipEventRecord(s->stage_ev, st) != hipSuccess)
+            return false;
+        batch = 0;
+        if (wait) return hipEventSynchronize(s->stage_ev) == hipSuccess;
+        s->stage_live = true;
+        return true;
+    };
     int64_t ko = 0, co = 0;
     for (int32_t i = 0; i < n; ++i) {
+        // a batch as large as the cache could see its own slots refilled
+        if (batch == s->capacity && !flush(true)) return FA_ERR_DEVICE;
         const int32_t slot = fetch_one(s, ids[i]);
         if (slot < 0) return FA_ERR_DEVICE;
         const int nn = s->ncp[ids[i]], p = s->deg[ids[i]];
         const int64_t kl = 3 * (nn + p + 1), cl = (int64_t)nn * nn * nn;
         co = align64(co);
         const float *src = s->slots + (int64_t)slot * s->slot_floats;
-        if (hipMemcpyAsync(dev_knots + ko, src, (size_t)kl * 4, hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(dev_ctrl + co, src + kl, (size_t)cl * 4, hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipEventRecord(s->ev[slot], st) != hipSuccess)
-            return FA_ERR_DEVICE;
-        s->ev_live[slot] = 1;
-        s->stats.bytes_h2d += (kl + cl) * 4;
         fa_block d{};
         for (int a = 0; a < 3; ++a) {
             d.ncp[a] = nn;
@@ -348,16 +349,20 @@ fa_status fa_store_stage(fa_store *s, const int32_t *ids, int32_t n, fa_block *d
             if (uni) fl |= 1u << a;
         }
         d.flags = fl;
-        s->desc_stage[i] = d;
+        fa::StageEntry &e = s->table[batch++];
+        e.slot_off = (int64_t)slot * s->slot_floats;
+        e.kdst = ko;
+        e.cdst = co;
+        e.kl = (int32_t)kl;
+        e.koff = (int32_t)knot_span(nn, p);
+        e.cl = cl;
+        e.dst = i;
+        e.desc = d;
+        s->stats.bytes_h2d += (kl + cl) * 4 + (int64_t)sizeof(fa_block);
         ko += kl;
         co += cl;
     }
-    if (hipMemcpyAsync(dev_blocks, s->desc_stage, (size_t)n * sizeof(fa_block),
-                       hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipEventRecord(s->desc_ev, st) != hipSuccess)
-        return FA_ERR_DEVICE;
-    s->desc_live = true;
-    s->stats.bytes_h2d += (int64_t)n * (int64_t)sizeof(fa_block);
+    if (!flush(false)) return FA_ERR_DEVICE;
     if (stats) *stats = s->stats;
     return FA_OK;
 }
