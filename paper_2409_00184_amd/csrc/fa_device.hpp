@@ -85,16 +85,19 @@ __device__ __forceinline__ void basis_ders(KP t, int s, float u, float (&N)[P + 
 
 // basis_ders<P> on a knot window held in registers: tw[m] = t[s-P+1+m],
 // m = 0..2P-1 (every knot the p+1 non-zero functions and their
-// derivatives touch), so all indices are compile-time constants.
+// derivatives touch), so all indices are compile-time constants.  The
+// derivative's denominators t[s+m] - t[s+m-P] (m = 1..P) are the ones of
+// the recursion's last degree, so their reciprocals are reused: P(P+1)/2
+// reciprocals per axis instead of P(P+1)/2 + 2P.
 template <int P>
 __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u,
                                                float (&N)[P + 1], float (&D)[P + 1]) {
-    float left[P + 1], right[P + 1], low[P + 1];
+    float left[P + 1], right[P + 1], low[P + 1], inv[P + 1];
     N[0] = 1.0f;
 #pragma unroll
     for (int k = 1; k <= P; ++k) {
-        left[k] = u - tw[P - k];       // t[s+1-k]
-        right[k] = tw[P - 1 + k] - u;  // t[s+k]
+        left[k] = u - tw[P - k];       // u - t[s+1-k]
+        right[k] = tw[P - 1 + k] - u;  // t[s+k] - u
         if (k == P) {
 #pragma unroll
             for (int r = 0; r < P; ++r) low[r] = N[r];
@@ -102,17 +105,22 @@ __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u
         float saved = 0.0f;
 #pragma unroll
         for (int r = 0; r < k; ++r) {
-            float q = N[r] * rcp(right[r + 1] + left[k - r]);
+            const float iv = rcp(right[r + 1] + left[k - r]);  // 1 / (t[s+r+1] - t[s+r+1-k])
+            if (k == P) inv[r + 1] = iv;
+            const float q = N[r] * iv;
             N[r] = saved + right[r + 1] * q;
             saved = left[k - r] * q;
         }
         N[k] = saved;
     }
+    // N'_{i,P} = P N_{i,P-1}/(t_{i+P}-t_i) - P N_{i+1,P-1}/(t_{i+P+1}-t_{i+1}),
+    // i = s-P+r: the denominators are t[s+r] - t[s+r-P] = 1/inv[r] and
+    // t[s+r+1] - t[s+r+1-P] = 1/inv[r+1].
 #pragma unroll
     for (int r = 0; r <= P; ++r) {
         float d = 0.0f;
-        if (r >= 1) d += low[r - 1] * rcp(tw[P - 1 + r] - tw[r - 1]);  // t[s+r] - t[s-P+r]
-        if (r <= P - 1) d -= low[r] * rcp(tw[P + r] - tw[r]);          // t[s+r+1] - t[s-P+r+1]
+        if (r >= 1) d += low[r - 1] * inv[r];
+        if (r <= P - 1) d -= low[r] * inv[r + 1];
         D[r] = float(P) * d;
     }
 }
