@@ -92,6 +92,9 @@ __device__ __forceinline__ void basis_ders(KP t, int s, float u, float (&N)[P + 
 template <int P>
 __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u,
                                                float (&N)[P + 1], float (&D)[P + 1]) {
+    // explicit fused operations only: every code path that inlines this
+    // computes bit-identical values
+#pragma clang fp contract(off)
     float left[P + 1], right[P + 1], low[P + 1], inv[P + 1];
     N[0] = 1.0f;
 #pragma unroll
@@ -108,7 +111,7 @@ __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u
             const float iv = rcp(right[r + 1] + left[k - r]);  // 1 / (t[s+r+1] - t[s+r+1-k])
             if (k == P) inv[r + 1] = iv;
             const float q = N[r] * iv;
-            N[r] = saved + right[r + 1] * q;
+            N[r] = fmaf(right[r + 1], q, saved);
             saved = left[k - r] * q;
         }
         N[k] = saved;
@@ -119,8 +122,8 @@ __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u
 #pragma unroll
     for (int r = 0; r <= P; ++r) {
         float d = 0.0f;
-        if (r >= 1) d += low[r - 1] * inv[r];
-        if (r <= P - 1) d -= low[r] * inv[r + 1];
+        if (r >= 1) d = low[r - 1] * inv[r];
+        if (r <= P - 1) d = fmaf(-low[r], inv[r + 1], d);
         D[r] = float(P) * d;
     }
 }

@@ -25,25 +25,120 @@ __device__ __forceinline__ Vec<N> ldv(const float *p) {
     return r;
 }
 
-// Span and register knot window tw[m] = t[s-P+1+m] of one axis.
-template <int P>
-__device__ __forceinline__ int axis_window(int n, const float *t, float u, bool uniform,
+// N consecutive 32-bit words at a byte offset of a buffer resource (the
+// base sits in scalar registers, the offset is one 32-bit VGPR; offsets past
+// the resource's size read as zero).
+template <int N>
+__device__ __forceinline__ Vec<N> bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    Vec<N> v;
+    if constexpr (N == 1) {
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        __builtin_memcpy(&v, &x, 4);
+    } else if constexpr (N == 2) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        __builtin_memcpy(&v, &x, 8);
+    } else if constexpr (N == 3) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+        __builtin_memcpy(&v, &x, 12);
+    } else if constexpr (N == 4) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        __builtin_memcpy(&v, &x, 16);
+    } else {
+        static_assert(N > 4 && N <= 8, "window of at most 8 words");
+        const Vec<4> lo = bload<4>(r, off);
+        const Vec<N - 4> hi = bload<N - 4>(r, off + 16u);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v.v[m] = lo.v[m];
+#pragma unroll
+        for (int m = 0; m < N - 4; ++m) v.v[4 + m] = hi.v[m];
+    }
+    return v;
+}
+
+// Raw buffer resource over `bytes` bytes at a wave-uniform base (gfx9
+// word 3: 32-bit data format, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    const uint64_t v = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    void *p = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
+}
+
+// Knot windows and lattice rows of one block, either through buffer
+// resources (the block is the same in every lane) or through plain 64-bit
+// addresses (lanes in different blocks).
+template <bool UNI>
+struct BlockLoads;
+
+template <>
+struct BlockLoads<true> {
+    __amdgpu_buffer_rsrc_t kr, cr;
+    __device__ BlockLoads(const float *knots, uint32_t nknots, const void *ctrl, uint32_t cbytes)
+        : kr(make_rsrc(knots, nknots * 4u)), cr(make_rsrc(ctrl, cbytes)) {}
+    template <int N>
+    __device__ __forceinline__ Vec<N> knots(uint32_t i) const { return bload<N>(kr, i * 4u); }
+    template <int N>
+    __device__ __forceinline__ Vec<N> rowf(uint32_t i) const { return bload<N>(cr, i * 4u); }
+    // N two-byte lattice values from element i: the words around them
+    // (reads past the lattice's end come back as zero)
+    template <int N>
+    __device__ __forceinline__ void half(uint32_t i, uint16_t (&h)[N]) const {
+        const uint32_t byte = i * 2u, w = byte & ~3u;
+        const int sh = (int)((byte >> 1) & 1u);
+        const Vec<(N + 2) / 2> v = bload<(N + 2) / 2>(cr, w);
+        uint16_t t[2 * ((N + 2) / 2)];
+        __builtin_memcpy(t, &v, sizeof(t));
+#pragma unroll
+        for (int k = 0; k < N; ++k) h[k] = sh ? t[k + 1] : t[k];
+    }
+};
+
+template <>
+struct BlockLoads<false> {
+    const float *kp;
+    const char *cp;
+    __device__ BlockLoads(const float *knots, uint32_t, const void *ctrl, uint32_t)
+        : kp(knots), cp(static_cast<const char *>(ctrl)) {}
+    template <int N>
+    __device__ __forceinline__ Vec<N> knots(uint32_t i) const { return ldv<N>(kp + i); }
+    template <int N>
+    __device__ __forceinline__ Vec<N> rowf(uint32_t i) const {
+        return ldv<N>(reinterpret_cast<const float *>(cp) + i);
+    }
+    template <int N>
+    __device__ __forceinline__ void half(uint32_t i, uint16_t (&h)[N]) const {
+        const uint16_t *p = reinterpret_cast<const uint16_t *>(cp) + i;
+#pragma unroll
+        for (int k = 0; k < N; ++k) h[k] = p[k];
+    }
+};
+
+// Span and register knot window tw[m] = t[s-P+1+m] of one axis (knots of
+// the axis start at element k0 of the block's knots).  Uniform knots: the
+// guess p + floor(u (n-p)) is off by at most one (and only within a few
+// ulps of a knot); one load of the knots around it covers the windows of
+// the guess and of both neighbours, and the comparisons with t[s0] and
+// t[s0+1] pick one (selects, no branch).
+template <int P, bool UNI>
+__device__ __forceinline__ int axis_window(const BlockLoads<UNI> &L, uint32_t k0, int n,
+                                           const float *t, float u, bool uniform,
                                            float (&tw)[2 * P]) {
     if (uniform) {
         int s0 = P + (int)(u * float(n - P));
         s0 = s0 > n - 1 ? n - 1 : s0;
-        // t[s0-P .. s0+P+1]: covers the windows of s0-1, s0, s0+1
-        const Vec<2 * P + 2> w = ldv<2 * P + 2>(t + s0 - P);
+        // t[s0-P .. s0+P+1] covers the windows of s0-1, s0 and s0+1
+        const Vec<2 * P + 2> w = L.template knots<2 * P + 2>(k0 + (uint32_t)(s0 - P));
         int d = 0;
-        if (s0 > P && u < w.v[P]) d = -1;                   // u < t[s0]
-        else if (s0 < n - 1 && u >= w.v[P + 1]) d = 1;      // u >= t[s0+1]
+        if (s0 > P && u < w.v[P]) d = -1;               // u < t[s0]
+        else if (s0 < n - 1 && u >= w.v[P + 1]) d = 1;  // u >= t[s0+1]
 #pragma unroll
         for (int m = 0; m < 2 * P; ++m)
             tw[m] = d < 0 ? w.v[m] : (d > 0 ? w.v[m + 2] : w.v[m + 1]);
         return s0 + d;
     }
     const int s = span_search(n, P, t, u);
-    const Vec<2 * P> w = ldv<2 * P>(t + s - P + 1);
+    const Vec<2 * P> w = L.template knots<2 * P>(k0 + (uint32_t)(s - P + 1));
 #pragma unroll
     for (int m = 0; m < 2 * P; ++m) tw[m] = w.v[m];
     return s;
@@ -56,35 +151,47 @@ struct BlockView {
     float scale;
 };
 
-template <int P, int DT>
+// UNI: the block is the same in every lane (its knots and lattice are read
+// through buffer resources).
+template <int P, int DT, bool UNI>
 __device__ __forceinline__ float4 query_block(const QueryLaunch &a, const BlockView &B,
                                               const float (&uu)[3]) {
     const float *tx = a.knots + B.knot_off;
-    const float *ty = tx + B.nx + P + 1;
-    const float *tz = ty + B.ny + P + 1;
+    const uint32_t kx = 0, ky = (uint32_t)B.nx + P + 1, kz = ky + (uint32_t)B.ny + P + 1;
+    const uint32_t nk = kz + (uint32_t)B.nz + P + 1;
+    constexpr uint32_t esz = DT == FA_F32 ? 4u : 2u;
+    const uint32_t nctrl = (uint32_t)B.nx * (uint32_t)B.ny * (uint32_t)B.nz;
+    const BlockLoads<UNI> L(tx, nk, static_cast<const char *>(a.ctrl) + B.ctrl_off * esz,
+                            nctrl * esz);
     float wx[2 * P], wy[2 * P], wz[2 * P];
-    const int sx = axis_window<P>(B.nx, tx, uu[0], B.flags & FA_FLAG_UNIFORM_X, wx);
-    const int sy = axis_window<P>(B.ny, ty, uu[1], B.flags & FA_FLAG_UNIFORM_Y, wy);
-    const int sz = axis_window<P>(B.nz, tz, uu[2], B.flags & FA_FLAG_UNIFORM_Z, wz);
+    const int sx = axis_window<P, UNI>(L, kx, B.nx, tx, uu[0], B.flags & FA_FLAG_UNIFORM_X, wx);
+    const int sy = axis_window<P, UNI>(L, ky, B.ny, tx + ky, uu[1], B.flags & FA_FLAG_UNIFORM_Y,
+                                       wy);
+    const int sz = axis_window<P, UNI>(L, kz, B.nz, tx + kz, uu[2], B.flags & FA_FLAG_UNIFORM_Z,
+                                       wz);
     float xB[P + 1], xD[P + 1], yB[P + 1], yD[P + 1], zB[P + 1], zD[P + 1];
     basis_ders_win<P>(wx, uu[0], xB, xD);
     basis_ders_win<P>(wy, uu[1], yB, yD);
     basis_ders_win<P>(wz, uu[2], zB, zD);
-    const int64_t base = B.ctrl_off + ((int64_t)(sx - P) * B.ny + (sy - P)) * B.nz + (sz - P);
+    // a block's lattice has at most 64^3 points: 32-bit offsets from its base
+    const uint32_t plane = (uint32_t)B.ny * (uint32_t)B.nz;
+    const uint32_t o0 = ((uint32_t)(sx - P) * (uint32_t)B.ny + (uint32_t)(sy - P)) *
+                            (uint32_t)B.nz + (uint32_t)(sz - P);
     float f = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
 #pragma unroll
     for (int i = 0; i <= P; ++i) {
         float uBB = 0.0f, uDB = 0.0f, uBD = 0.0f;
 #pragma unroll
         for (int j = 0; j <= P; ++j) {
-            const int64_t row = base + ((int64_t)i * B.ny + j) * B.nz;
+            const uint32_t row = o0 + (uint32_t)i * plane + (uint32_t)j * (uint32_t)B.nz;
             float c[P + 1];
             if (DT == FA_F32) {
-                const Vec<P + 1> r = ldv<P + 1>(static_cast<const float *>(a.ctrl) + row);
+                const Vec<P + 1> r = L.template rowf<P + 1>(row);
 #pragma unroll
                 for (int k = 0; k <= P; ++k) c[k] = r.v[k];
             } else {
-                const uint16_t *h = static_cast<const uint16_t *>(a.ctrl) + row;
+                uint16_t h[P + 1];
+                L.template half<P + 1>(row, h);
 #pragma unroll
                 for (int k = 0; k <= P; ++k)
                     c[k] = (DT == FA_BF16 ? bf16_to_f32(h[k]) : f16_to_f32(h[k]));
@@ -134,12 +241,12 @@ __device__ __forceinline__ BlockView view_of(const fa_block &B) {
     return v;
 }
 
-template <int DT>
+template <int DT, bool UNI>
 __device__ __forceinline__ float4 query_any(const QueryLaunch &a, const BlockView &V, int p,
                                             const float (&uu)[3]) {
-    if (p == 3) return query_block<3, DT>(a, V, uu);
-    if (p == 2) return query_block<2, DT>(a, V, uu);
-    return query_block<1, DT>(a, V, uu);
+    if (p == 3) return query_block<3, DT, UNI>(a, V, uu);
+    if (p == 2) return query_block<2, DT, UNI>(a, V, uu);
+    return query_block<1, DT, UNI>(a, V, uu);
 }
 
 
@@ -161,11 +268,11 @@ __device__ __forceinline__ float4 eval_point(const QueryLaunch &a, float x, floa
         // wave-uniform block: scalar descriptor loads, no divergence
         if (blk0 >= 0) {
             const fa_block &B = a.blocks[blk0];
-            r = query_any<DT>(a, view_of(B), B.degree[0], uu);
+            r = query_any<DT, true>(a, view_of(B), B.degree[0], uu);
         }
     } else if (blk >= 0) {
         const fa_block &B = a.blocks[blk];
-        r = query_any<DT>(a, view_of(B), B.degree[0], uu);
+        r = query_any<DT, false>(a, view_of(B), B.degree[0], uu);
     }
     r.y *= a.rscale[0];
     r.z *= a.rscale[1];

@@ -307,6 +307,9 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
             const u16x8 aBD = *reinterpret_cast<const u16x8 *>(R2 + (2 * kUC * kRows + row) * kR2Stride + 8 * g);
             float *stage = R1B + wave * (16 * kStageStride);
             const int w = col0 + lane;
+            // whole 64-column tile, rows of a multiple of 4 floats: every
+            // 4-voxel group is a 16-byte aligned store
+            const bool vec_store = col0 + kWave <= a.rz && (a.rz & 3) == 0;
             for (int ch = 0; ch < 4; ++ch) {
                 if (!((a.mask >> ch) & 1u)) continue;
                 const u16x8 &aa = ch == 1 ? aDB : (ch == 2 ? aBD : aBB);
@@ -322,13 +325,29 @@ __device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0,
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const int ub = u0 + 4 * wave;
-                float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz + w;
-                const bool wok = w < a.rz;
+                if (vec_store) {
+                    // 16-byte non-temporal stores: a quarter-wave writes one
+                    // whole 256-byte z row
+                    float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz +
+                                col0 + 4 * l16;
 #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) {
-                    const float val = stage[rr * kStageStride + lane];
-                    if (wok && ub + (rr >> 2) < a.rx && (rr & 3) < nrows)
-                        oc[(rr >> 2) * plane + (rr & 3) * a.rz] = val;
+                    for (int it = 0; it < 4; ++it) {
+                        const int rr = 4 * it + g;
+                        const f32x4 val =
+                            *reinterpret_cast<const f32x4 *>(stage + rr * kStageStride + 4 * l16);
+                        if (ub + it < a.rx && g < nrows)
+                            __builtin_nontemporal_store(
+                                val, reinterpret_cast<f32x4 *>(oc + it * plane + g * a.rz));
+                    }
+                } else {
+                    float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz + w;
+                    const bool wok = w < a.rz;
+#pragma unroll
+                    for (int rr = 0; rr < 16; ++rr) {
+                        const float val = stage[rr * kStageStride + lane];
+                        if (wok && ub + (rr >> 2) < a.rx && (rr & 3) < nrows)
+                            oc[(rr >> 2) * plane + (rr & 3) * a.rz] = val;
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();

@@ -68,7 +68,10 @@ __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
 #ifndef FA_RAY_TY
 #define FA_RAY_TY 4
 #endif
-constexpr int kTX = FA_RAY_TX, kTY = FA_RAY_TY;
+#ifndef FA_RAY_SYNC
+#define FA_RAY_SYNC 1
+#endif
+constexpr int kTX = FA_RAY_TX, kTY = FA_RAY_TY, kSync = FA_RAY_SYNC;
 
 template <int DT>
 __global__ __launch_bounds__(64 * kTX * kTY) void query_rays_kernel(QueryLaunch a) {
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(64 * kTX * kTY) void query_rays_kernel(QueryLaunch 
             query_sample<DT>(a, ray * a.rk + k, ray_ok && k < a.rk);
             // keep the rays of the tile at the same depth; no data is exchanged,
             // so a bare barrier (outputs stay in flight)
-            __builtin_amdgcn_s_barrier();
+            if ((k0 / kWave) % kSync == kSync - 1) __builtin_amdgcn_s_barrier();
         }
     }
 }
