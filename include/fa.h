@@ -336,6 +336,21 @@ fa_status fa_model_errors(const fa_block *blocks, int32_t nblocks, const float *
                           const float *samples, float *decoded, float *errs,
                           int64_t errs_stride, void *stream);
 
+/*
+ * Mean-squared-error step of a fit (the loss whose gradient the adjoint
+ * carries back to the control points, Alg. 1's model fit): for every block
+ * b and voxel v of its value decode,
+ *   grad[b][v] = grad_scale * (decoded - samples),
+ *   sumsq[b]   = sum_v (decoded - samples)^2   (FP64, fixed order).
+ * With grad_scale = 2 / M (M = all voxels) grad is dLoss/ddecoded of
+ * Loss = sum_b sumsq[b] / M.  grad may alias decoded.  All device pointers:
+ * decoded, samples, grad FP32 [nblocks][vox]; sumsq FP64 [nblocks].
+ * Deterministic.  FA_ERR_INVALID_ARG for null pointers, nblocks or vox <= 0,
+ * a non-finite grad_scale.
+ */
+fa_status fa_mse_grad(const float *decoded, const float *samples, int32_t nblocks, int64_t vox,
+                      float grad_scale, float *grad, double *sumsq, void *stream);
+
 /* Bytes of device workspace fa_ncp_search needs (-1 for invalid sizes). */
 int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t degree,
                                 int32_t ncp_hi);

@@ -101,6 +101,8 @@ def _load():
     L.fa_render_rays.restype = ctypes.c_int
     L.fa_render_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32,
                                  vp, vp, vp, vp]
+    L.fa_mse_grad.restype = ctypes.c_int
+    L.fa_mse_grad.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, vp]
     L.fa_fit_workspace.restype = i64
     L.fa_fit_workspace.argtypes = [i32, vp, i32]
     L.fa_fit_blocks.restype = ctypes.c_int
@@ -617,6 +619,32 @@ class FADecode(torch.autograd.Function):
     def backward(ctx, g):
         gc = decode_backward(ctx.models, ctx.res, g.contiguous(), ctx.mask)
         return gc, None, None, None, None
+
+
+class FAFitMSE(torch.autograd.Function):
+    """Loss = mean over all voxels of (B(ctrl) - y)^2 in three HIP launches:
+    value decode, fused residual / loss / cotangent (fa_mse_grad), and in
+    backward the adjoint B^T of the cotangent.  y: [nblocks, *res] float32."""
+
+    @staticmethod
+    def forward(ctx, ctrl, models, res, y, plan):
+        models.set_ctrl(ctrl.detach())
+        f = decode(models, res, 1, plan=plan)
+        nvox = int(np.prod(res))
+        m_all = models.nblocks * nvox
+        sumsq = torch.empty(models.nblocks, dtype=torch.float64, device=models.device)
+        st = lib.fa_mse_grad(_ptr(f), _ptr(y), models.nblocks, nvox, 2.0 / m_all, _ptr(f),
+                             _ptr(sumsq), _stream())
+        _check("fa_mse_grad", st)
+        ctx.models, ctx.res = models, res
+        ctx.save_for_backward(f)  # now holds the cotangent 2 (f - y) / M
+        return (sumsq.sum() / m_all).to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        gc = decode_backward(ctx.models, ctx.res, g, 1)
+        return gc * gl, None, None, None, None
 
 
 def capture(fn, warmup=1):

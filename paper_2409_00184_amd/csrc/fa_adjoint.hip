@@ -14,17 +14,27 @@
 // HB/H2/H3 of that plane to LDS, contracts y over each j's contiguous v
 // support, then z over each k's w support, and stores the plane of G once.
 // Fixed summation order, no atomics: the result is deterministic.
+//
+// Value-only cotangents (the fit's residual) use 8-wave workgroups with a
+// third of the LDS, and split each micro-model's control planes between
+// segments: a segment owns planes [i0, i1), streams exactly the x positions
+// whose basis touches them (neighbouring segments re-read the p-plane
+// overlap) and stores only its own planes, so several segments stream at
+// once on a CU and every plane is still written by one workgroup.
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
 namespace fa {
 namespace {
 
-constexpr int kAdjWaves = 16;
 constexpr int kAdjMaxYZ = 64;                      // res[1], res[2] limit
-constexpr int kAdjRows = kAdjMaxYZ / kAdjWaves;    // y rows per wave
 constexpr int kPlane = kAdjMaxYZ * kWave;          // one (v, w) plane
 
+// waves per workgroup: 16 with derivative cotangents, 8 for value only
+template <bool DER>
+constexpr int adj_waves() { return DER ? 16 : 8; }
+
+template <bool DER>
 struct AdjSmem {
     float4 xB[kMaxRes], xD[kMaxRes];
     int xS[kMaxRes];
@@ -35,8 +45,8 @@ struct AdjSmem {
     int jva[FA_MAX_NCP], jvb[FA_MAX_NCP];  // v support of control row j
     int kwa[FA_MAX_NCP], kwb[FA_MAX_NCP];  // w support of control column k
     float kn[kMaxKnotsPerBlock + 4];
-    float H[3][kPlane];                    // HB, H2, H3 of the plane being emitted
-    float K[2][FA_MAX_NCP * kWave];        // KB, K3
+    float H[DER ? 3 : 1][kPlane];          // HB, H2, H3 of the plane being emitted
+    float K[DER ? 2 : 1][FA_MAX_NCP * kWave];  // KB, K3
 };
 
 __device__ __forceinline__ float comp4(const float4 &v, int r) {
@@ -63,7 +73,10 @@ __device__ __forceinline__ void tab_axis(const float *t, int n, int R, int idx, 
 // DER: cotangents of derivative channels present (H2, H3, K3 in use)
 template <int P, bool DER>
 __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry, int rz,
-                          uint32_t mask, int nch, const float *g, float *G, int b, AdjSmem &sm) {
+                          uint32_t mask, int nch, const float *g, float *G, int b, int seg,
+                          int nseg, AdjSmem<DER> &sm) {
+    constexpr int kAdjWaves = adj_waves<DER>();
+    constexpr int kAdjRows = kAdjMaxYZ / kAdjWaves;  // y rows per wave
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
@@ -160,8 +173,10 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
         }
         lds_barrier();
     };
+    // the control planes this segment owns
+    const int i0 = (int)((int64_t)seg * nx / nseg), i1 = (int)((int64_t)(seg + 1) * nx / nseg);
     auto advance = [&]() {  // plane top-P is final; shift the windows by one
-        if (top - P >= 0) emit(top - P);
+        if (top - P >= i0 && top - P < i1) emit(top - P);
 #pragma unroll
         for (int m = 0; m < kAdjRows; ++m) {
 #pragma unroll
@@ -195,49 +210,57 @@ __device__ void adj_block(const fa_block &B, const float *knots, int rx, int ry,
             f3[m] = (ok && DER && (mask & 8u)) ? gp[choff[3]] : 0.0f;
         }
     };
-    fetch(0, g0, g1, g2, g3);
-    for (int u = 0; u < rx; ++u) {
-        fetch(u + 1, n0, n1, n2, n3);
-        const int s = sm.xS[u];
-        while (top < s) advance();  // uniform over the workgroup
-        const float4 bx = sm.xB[u], dx = sm.xD[u];
+    // x positions whose basis touches [i0, i1): spans s(u) in [i0, i1 - 1 + P]
+    // (s(u) is non-decreasing in u)
+    int ulo = 0, uhi = rx - 1;
+    while (ulo < rx && sm.xS[ulo] < i0) ++ulo;
+    while (uhi >= ulo && sm.xS[uhi] - P > i1 - 1) --uhi;
+    if (i0 < i1) {
+        fetch(ulo, g0, g1, g2, g3);
+        for (int u = ulo; u <= uhi; ++u) {
+            if (u + 1 <= uhi) fetch(u + 1, n0, n1, n2, n3);
+            const int s = sm.xS[u];
+            while (top < s) advance();  // uniform over the workgroup
+            const float4 bx = sm.xB[u], dx = sm.xD[u];
 #pragma unroll
-        for (int m = 0; m < kAdjRows; ++m) {
+            for (int m = 0; m < kAdjRows; ++m) {
 #pragma unroll
-            for (int r = 0; r <= P; ++r) {
-                hB[m][r] = fmaf(comp4(bx, r), g0[m], hB[m][r]);
-                if (DER) {
-                    hB[m][r] = fmaf(comp4(dx, r), g1[m], hB[m][r]);
-                    h2[m][r] = fmaf(comp4(bx, r), g2[m], h2[m][r]);
-                    h3[m][r] = fmaf(comp4(bx, r), g3[m], h3[m][r]);
+                for (int r = 0; r <= P; ++r) {
+                    hB[m][r] = fmaf(comp4(bx, r), g0[m], hB[m][r]);
+                    if (DER) {
+                        hB[m][r] = fmaf(comp4(dx, r), g1[m], hB[m][r]);
+                        h2[m][r] = fmaf(comp4(bx, r), g2[m], h2[m][r]);
+                        h3[m][r] = fmaf(comp4(bx, r), g3[m], h3[m][r]);
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int m = 0; m < kAdjRows; ++m) {
-            g0[m] = n0[m];
-            g1[m] = n1[m];
-            g2[m] = n2[m];
-            g3[m] = n3[m];
+            for (int m = 0; m < kAdjRows; ++m) {
+                g0[m] = n0[m];
+                g1[m] = n1[m];
+                g2[m] = n2[m];
+                g3[m] = n3[m];
+            }
         }
+        // the owned planes not emitted yet (also those no x position touches)
+        while (top - P < i1) advance();
     }
-    // the last P+1 planes (and any never reached) are final now
-    while (top < nx + P) advance();
 }
 
 template <bool DER>
-__global__ __launch_bounds__(1024) void adjoint_kernel(const fa_block *blocks, int nblocks,
-                                                     const float *knots, int rx, int ry, int rz,
-                                                     uint32_t mask, int nch, const float *g,
-                                                     float *G) {
+__global__ __launch_bounds__(64 * adj_waves<DER>()) void adjoint_kernel(
+    const fa_block *blocks, int nblocks, int nseg, const float *knots, int rx, int ry, int rz,
+    uint32_t mask, int nch, const float *g, float *G) {
     extern __shared__ float4 dyn_lds[];
-    AdjSmem &sm = *reinterpret_cast<AdjSmem *>(dyn_lds);
-    for (int b = xcd_order(blockIdx.x, gridDim.x); b < nblocks; b += gridDim.x) {
+    AdjSmem<DER> &sm = *reinterpret_cast<AdjSmem<DER> *>(dyn_lds);
+    const int64_t items = (int64_t)nblocks * nseg;
+    for (int64_t it = xcd_order(blockIdx.x, gridDim.x); it < items; it += gridDim.x) {
+        const int b = (int)(it / nseg), seg = (int)(it - (int64_t)b * nseg);
         const fa_block &B = blocks[b];
         const int p = B.degree[0];
-        if (p == 3) adj_block<3, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
-        else if (p == 2) adj_block<2, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
-        else adj_block<1, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, sm);
+        if (p == 3) adj_block<3, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, seg, nseg, sm);
+        else if (p == 2) adj_block<2, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, seg, nseg, sm);
+        else adj_block<1, DER>(B, knots, rx, ry, rz, mask, nch, g, G, b, seg, nseg, sm);
         lds_barrier();
     }
 }
@@ -249,25 +272,32 @@ hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knot
                           hipStream_t s) {
     const bool der = (mask & 14u) != 0;
     const int nch = __builtin_popcount(mask & 15u);
-    const size_t lds = sizeof(AdjSmem);
-    // raise the dynamic LDS limit once per process (before any graph capture)
+    // raise the dynamic LDS limits once per process (before any graph capture)
     static const hipError_t attr = [] {
         hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_kernel<true>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(AdjSmem));
+                                            (int)sizeof(AdjSmem<true>));
         hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_kernel<false>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(AdjSmem));
+                                            (int)sizeof(AdjSmem<false>));
         return e1 != hipSuccess ? e1 : e2;
     }();
     if (attr != hipSuccess) return attr;
-    const int grid = nblocks < 65536 ? nblocks : 65536;
-    if (der)
-        hipLaunchKernelGGL((adjoint_kernel<true>), dim3(grid), dim3(64 * kAdjWaves), lds, s,
-                           blocks, nblocks, knots, rx, ry, rz, mask, nch, g, G);
-    else
-        hipLaunchKernelGGL((adjoint_kernel<false>), dim3(grid), dim3(64 * kAdjWaves), lds, s,
-                           blocks, nblocks, knots, rx, ry, rz, mask, nch, g, G);
+    if (der) {
+        const int grid = nblocks < 65536 ? nblocks : 65536;
+        hipLaunchKernelGGL((adjoint_kernel<true>), dim3(grid), dim3(64 * adj_waves<true>()),
+                           sizeof(AdjSmem<true>), s, blocks, nblocks, 1, knots, rx, ry, rz, mask,
+                           nch, g, G);
+    } else {
+        // two segments per micro-model while the batch alone would not give
+        // every CU several workgroups
+        const int nseg = nblocks < 1024 ? 2 : 1;
+        const int64_t items = (int64_t)nblocks * nseg;
+        const int grid = (int)(items < 65536 ? items : 65536);
+        hipLaunchKernelGGL((adjoint_kernel<false>), dim3(grid), dim3(64 * adj_waves<false>()),
+                           sizeof(AdjSmem<false>), s, blocks, nblocks, nseg, knots, rx, ry, rz,
+                           mask, nch, g, G);
+    }
     return hipGetLastError();
 }
 

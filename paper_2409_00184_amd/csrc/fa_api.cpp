@@ -393,6 +393,16 @@ fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctr
 }
 
 
+fa_status fa_mse_grad(const float *decoded, const float *samples, int32_t nblocks, int64_t vox,
+                      float grad_scale, float *grad, double *sumsq, void *stream) {
+    if (!decoded || !samples || !grad || !sumsq || nblocks <= 0 || vox <= 0 ||
+        !std::isfinite(grad_scale))
+        return FA_ERR_INVALID_ARG;
+    hipError_t e = launch_mse_grad(decoded, samples, vox, nblocks, grad_scale, grad, sumsq,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 int64_t fa_fit_workspace(int32_t nblocks, const int32_t res[3], int32_t max_ncp) {
     if (nblocks <= 0 || !res_ok(res) || max_ncp < 2) return -1;
     return fit_workspace_bytes(nblocks, res[0], res[1], max_ncp);

@@ -303,6 +303,49 @@ __global__ __launch_bounds__(kFitThreads) void residual_kernel(const float *y, c
     }
 }
 
+// Least-squares loss of a fit and its cotangent in one pass (the residual
+// step between the forward decode and the adjoint): per block b,
+//   grad[b][v] = scale * (f[b][v] - y[b][v]),  sumsq[b] = sum_v (f - y)^2
+// (FP64 sum, fixed order).
+__global__ __launch_bounds__(kFitThreads) void mse_grad_kernel(const float *f, const float *y,
+                                                                int64_t vox, int nblocks,
+                                                                float scale, float *grad,
+                                                                double *sumsq) {
+    __shared__ double ssum[kFitThreads];
+    const int tid = threadIdx.x;
+    for (int bi = blockIdx.x; bi < nblocks; bi += gridDim.x) {
+        const int64_t o = (int64_t)bi * vox;
+        double acc = 0.0;
+        if ((vox & 3) == 0) {
+            const f32x4 *f4 = reinterpret_cast<const f32x4 *>(f + o);
+            const f32x4 *y4 = reinterpret_cast<const f32x4 *>(y + o);
+            f32x4 *g4 = reinterpret_cast<f32x4 *>(grad + o);
+            for (int64_t i = tid; i < vox / 4; i += kFitThreads) {
+                const f32x4 a = __builtin_nontemporal_load(f4 + i);
+                const f32x4 c = __builtin_nontemporal_load(y4 + i);
+                const f32x4 r = a - c;
+                acc += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z +
+                       (double)r.w * r.w;
+                g4[i] = r * scale;
+            }
+        } else {
+            for (int64_t i = tid; i < vox; i += kFitThreads) {
+                const float r = f[o + i] - y[o + i];
+                acc += (double)r * r;
+                grad[o + i] = r * scale;
+            }
+        }
+        ssum[tid] = acc;
+        __syncthreads();
+        for (int w = kFitThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) ssum[tid] += ssum[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) sumsq[bi] = ssum[0];
+        __syncthreads();
+    }
+}
+
 // Descriptors and shared knots of one candidate NCP (same n and p on every
 // axis, clamped uniform knots t_{p+j} = j / (n - p)); lattices at `cstride`.
 __global__ void candidate_kernel(fa_block *desc, float *knots, int nblocks, int n, int p,
@@ -371,6 +414,14 @@ hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblo
     const int grid = nblocks < 65536 ? nblocks : 65536;
     hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(kFitThreads), 0, s, y, f, vox, nblocks,
                        errs, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float *f, const float *y, int64_t vox, int nblocks, float scale,
+                           float *grad, double *sumsq, hipStream_t s) {
+    const int grid = nblocks < 65536 ? nblocks : 65536;
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(grid), dim3(kFitThreads), 0, s, f, y, vox, nblocks,
+                       scale, grad, sumsq);
     return hipGetLastError();
 }
 

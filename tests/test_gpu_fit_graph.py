@@ -82,6 +82,37 @@ def test_fit_gradient_vs_oracle_and_fd(fa, nblocks, resn):
         assert abs(fd - grad[e]) <= 1e-4 * abs(fd) + 1e-3 * ga[e] + 1e-12, (e, fd, grad[e])
 
 
+@pytest.mark.parametrize("nblocks,resn", [(6, 24), (256, 64)])
+def test_fused_mse_gradient_vs_oracle(fa, nblocks, resn):
+    """The fused loss (decode, fa_mse_grad, adjoint) gives the FP64 oracle's
+    loss and gradient under the same bounds as the torch-composed loss, and
+    agrees with that loss to FP32 rounding."""
+    say("fused mse", nblocks, resn)
+    b, y = fi.config_c4(nblocks=nblocks, res=resn)
+    res = (resn,) * 3
+    g = fi.rng(62)
+    P0 = (0.5 * g.normal(size=b.ctrl.size)).astype(np.float32)
+    m = models(b)
+    plan = fa.Plan(m, res)
+    ctrl = torch.as_tensor(P0, device="cuda").requires_grad_(True)
+    yt = torch.as_tensor(y, device="cuda").reshape(b.nblocks, *res).contiguous()
+    loss = fa.FAFitMSE.apply(ctrl, m, res, yt, plan)
+    loss.backward()
+    grad = ctrl.grad.detach().cpu().numpy().astype(np.float64)
+    go, ga, lo, _ = _oracle_grad(b, P0, y, res)
+    assert abs(float(loss) - lo) <= 1e-5 * lo
+    valid = np.zeros(b.ctrl.size, bool)
+    for k in range(b.nblocks):
+        o = int(b.ctrl_off[k])
+        valid[o:o + int(np.prod(b.ncp[k]))] = True
+    err = np.abs(grad - go)[valid]
+    lim = 256 * U32 * ga[valid] + 1e-30
+    assert np.all(err <= lim), float((err / lim).max())
+    _, g2, l2 = _fit_case(fa, b, y, P0, res)
+    assert abs(float(loss) - l2) <= 1e-5 * l2
+    assert np.abs(grad - g2)[valid].max() <= 1e-5 * np.abs(g2[valid]).max()
+
+
 def test_fit_converges(fa):
     """A few Adam steps on C4-shaped blocks lower the loss steadily."""
     say("fit converges")
