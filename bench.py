@@ -121,6 +121,39 @@ def cpu_baseline_decode(batch, res, target_s=15.0):
                       f"value+grad, FP64, {dt:.1f} s"}
 
 
+def cpu_baseline_fit(batch, y, res, target_s=15.0):
+    """The FP64 oracle's fit iteration (decode, residual, adjoint B^T r) on a
+    seeded sample of whole blocks, as iterations/s of the whole batch."""
+    import numpy as np
+
+    import oracle
+    th = oracle.nthreads_default()
+    g = np.random.Generator(np.random.PCG64(98))
+    order = g.permutation(batch.nblocks)
+    ob = oracle.Blocks(batch.ncp, batch.deg, batch.knot_off, batch.ctrl_off, batch.knots,
+                       batch.ctrl)
+
+    def run(k):
+        sel = order[:k]
+        sub = oracle.Blocks(ob.ncp[sel], ob.deg[sel], ob.knot_off[sel], ob.ctrl_off[sel],
+                            ob.knots, ob.ctrl)
+        f = oracle.decode_blocks(sub, res, 1, nthreads=th)
+        r = f - np.asarray(y, np.float64).reshape(batch.nblocks, 1, *res)[sel]
+        oracle.decode_adjoint(sub, res, r, 1, nthreads=th)
+
+    t0 = time.perf_counter()
+    run(1)
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(batch.nblocks, target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    run(k)
+    dt = time.perf_counter() - t0
+    return {"value": k / batch.nblocks / dt, "unit": "iterations/s", "cores": th,
+            "kind": "oracle",
+            "sample": f"{k} of {batch.nblocks} blocks (seeded): FP64 value decode, residual and "
+                      f"adjoint, {dt:.1f} s, scaled to the whole batch (optimizer step excluded)"}
+
+
 def err_vs_oracle_decode(batch, out, res, nsample=20000, src=None):
     """Max |gpu - FP64| / max |FP64| per channel on seeded voxels."""
     import numpy as np
@@ -772,7 +805,9 @@ def bench_c4(args):
                     "forward_decode": {"ms": fev, "GB/s": (nvox * 4 + lat) / (fev * 1e-3) / 1e9},
                     "adjoint": {"ms": bev, "GB/s": (nvox * 4 + lat) / (bev * 1e-3) / 1e9},
                     "torch_composed_loss_ms_per_step": ms_t,
-                    "loss_first_last": [first, last]})
+                    "loss_first_last": [first, last]},
+                   ) | ({} if args.no_cpu_baseline else
+                        {"cpu_baseline": cpu_baseline_fit(b, y, res, args.cpu_seconds)})
 
 
 # ------------------------------------------------------------------ C5
@@ -807,11 +842,14 @@ def bench_c5(args):
     for v in variants.values():
         v["speedup_vs_f32"] = base / v["ms_per_step"]
     best = variants["bf16_mfma"]
-    return _common(args, METRIC, best["value"], "voxels/s", best["ms_per_step"], "bf16",
+    line = _common(args, METRIC, best["value"], "voxels/s", best["ms_per_step"], "bf16",
                    "C5 precision: 4096 micro-models of 32^3 control points (k^-5/3), cubic, "
                    "64^3 voxels each (1.07e9), value + 3 gradients; BF16/FP16 lattices with "
                    "per-block max-abs scale on MFMA (FP32 accumulation) vs FP32",
                    {"roofline": best["roofline"], "variants": variants})
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_decode(b, res, args.cpu_seconds)
+    return line
 
 
 def probe(args):

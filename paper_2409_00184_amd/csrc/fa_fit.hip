@@ -16,11 +16,12 @@
 // badly conditioned).  Three kernels, FP64 throughout:
 //   fit_pinv: X_a of every (block, axis), one workgroup each, into the
 //           caller's workspace,
-//   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (one thread per
-//           (x, y) line, lines staged in LDS, T in the workspace),
+//   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (chunks of 256
+//           (x, y) lines staged in LDS, T in the workspace),
 //   fit_xy: for each k, P[:, :, k] = X_x T[b][k] X_y^T        (one workgroup
 //           per (block, k), the slice in LDS),
-// and the lattice is rounded to FP32 once.
+// the dense products of fit_z and fit_xy on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64), and the lattice rounded to FP32 once.
 // residual kernel: one workgroup per block reduces y - f to (max |r|,
 // sqrt(mean r^2)) in a fixed order (deterministic).
 #include <algorithm>
@@ -151,31 +152,45 @@ __global__ __launch_bounds__(kFitThreads) void fit_pinv_kernel(const fa_block *b
                                                                double *Xg) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     PinvSmem &sm = *reinterpret_cast<PinvSmem *>(smem_raw);
-    const int R[3] = {r0, r1, r2};
     for (int64_t item = blockIdx.x; item < (int64_t)nblocks * 3; item += gridDim.x) {
         const int bi = (int)(item / 3), a = (int)(item - (int64_t)bi * 3);
         const fa_block b = blocks[bi];
-        const int n = b.ncp[a];
-        build_pinv(sm.w, axis_knots(knots, b, a), n, b.degree[a], R[a], &sm.X[0][0], kFitR, 1);
+        const int n = a == 0 ? b.ncp[0] : (a == 1 ? b.ncp[1] : b.ncp[2]);
+        const int p = a == 0 ? b.degree[0] : (a == 1 ? b.degree[1] : b.degree[2]);
+        const int Ra = a == 0 ? r0 : (a == 1 ? r1 : r2);
+        build_pinv(sm.w, axis_knots(knots, b, a), n, p, Ra, &sm.X[0][0], kFitR, 1);
         double *dst = Xg + item * kPinvStride;
         for (int e = threadIdx.x; e < n * kFitR; e += kFitThreads) dst[e] = (&sm.X[0][0])[e];
         __syncthreads();
     }
 }
 
+// FP64 matrix-core contraction tiles: v_mfma_f64_16x16x4f64 takes
+// A[l%16][l/16] and B[l/16][l%16] from lane l and returns D[4r + l/16][l%16]
+// in component r (layout checked on the device).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kXS = kFitR + 1;  // padded row of an LDS matrix (doubles)
+
 struct FitZSmem {
-    double X[kFitN][kFitR];                 // X_z[k][z]
-    float ys[kFitThreads][kFitR + 1];       // staged lines (padded)
+    double X[kFitN][kXS];                 // X_z[k][z]
+    float ys[kFitThreads][kFitR + 1];     // staged lines (padded)
 };
 
-// T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y, one thread per line
+// T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y: per chunk of 256
+// lines, a (n_z x R2) x (R2 x 256) product on the FP64 matrix cores.
 __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
                                                             const float *knots, int r0, int r1,
                                                             int r2, int max_n, const float *y,
                                                             const double *Xg, double *T) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitZSmem &sm = *reinterpret_cast<FitZSmem *>(smem_raw);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
     const int64_t lines = (int64_t)r0 * r1;
     const int chunks = (int)((lines + kFitThreads - 1) / kFitThreads);
     for (int64_t item = blockIdx.x; item < (int64_t)nblocks * chunks; item += gridDim.x) {
@@ -185,7 +200,10 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
         const int nz = b.ncp[2];
         if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
         const double *Xz = Xg + ((int64_t)bi * 3 + 2) * kPinvStride;
-        for (int e = tid; e < nz * kFitR; e += kFitThreads) (&sm.X[0][0])[e] = Xz[e];
+        for (int e = tid; e < nz * kFitR; e += kFitThreads) {
+            const int k = e / kFitR;
+            sm.X[k][e - k * kFitR] = Xz[e];
+        }
         const int cl = (int)(lines - l0 < kFitThreads ? lines - l0 : kFitThreads);
         const float *yb = y + ((int64_t)bi * lines + l0) * r2;
         for (int e = tid; e < cl * r2; e += kFitThreads) {
@@ -193,67 +211,138 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
             sm.ys[li][e - li * r2] = yb[e];
         }
         __syncthreads();
-        if (tid < cl) {
-            double *Tb = T + (int64_t)bi * max_n * lines + l0 + tid;
-            for (int k = 0; k < nz; ++k) {
-                double acc = 0.0;
-                for (int z = 0; z < r2; ++z) acc += sm.X[k][z] * (double)sm.ys[tid][z];
-                Tb[(int64_t)k * lines] = acc;
+        const int mt = (nz + 15) >> 4, nt = (cl + 15) >> 4, ksteps = (r2 + 3) >> 2;
+        const int nst = (nt + 3) >> 2;  // strips of 4 line tiles sharing the A operand
+        double *Tb = T + (int64_t)bi * max_n * lines + l0;
+        for (int unit = wave; unit < mt * nst; unit += kFitThreads / 64) {
+            const int ti = unit / nst, tj0 = 4 * (unit - ti * nst);
+            const int k = 16 * ti + lr;
+            f64x4 acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < ksteps; ++ks) {
+                const int z = 4 * ks + lk;
+                const bool zok = z < r2;
+                const double av = (k < nz && zok) ? sm.X[k][z] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int li = 16 * (tj0 + q) + lr;
+                    const double bv = (li < cl && zok) ? (double)sm.ys[li][z] : 0.0;
+                    acc[q] = mfma64(av, bv, acc[q]);  // four independent chains
+                }
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int kk = 16 * ti + 4 * r + lk, ll = 16 * (tj0 + q) + lr;
+                    if (kk < nz && ll < cl) Tb[(int64_t)kk * lines + ll] = acc[q][r];
+                }
         }
         __syncthreads();
     }
 }
 
 struct FitXYSmem {
-    double Xx[kFitN][kFitR];      // X_x[i][x]
-    double XyT[kFitR][kFitN + 1]; // X_y transposed: XyT[y][j]
-    double S[kFitR][kFitR];       // slice T[b][k] as [x][y]
-    double U[kFitN][kFitR];       // X_x S
+    double Xx[kFitN][kXS];  // X_x[i][x]
+    double Xy[kFitN][kXS];  // X_y[j][y]
+    double S[kFitR][kXS];   // slice T[b][k] as [x][y]
+    double U[kFitN][kXS];   // X_x S
 };
 
+// For each k: P[:, :, k] = X_x T[b][k] X_y^T, two products on the FP64
+// matrix cores (U = X_x S in LDS, then U X_y^T), one workgroup per (b, k).
 __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int r0, int r1,
-                                                             int max_n, const double *Xg,
-                                                             const double *T, float *ctrl) {
+                                                             int max_n, int kgroup,
+                                                             const double *Xg, const double *T,
+                                                             float *ctrl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitXYSmem &sm = *reinterpret_cast<FitXYSmem *>(smem_raw);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int kWaves = kFitThreads / 64;
     const int64_t lines = (int64_t)r0 * r1;
-    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * max_n; item += gridDim.x) {
-        const int bi = (int)(item / max_n);
-        const int k = (int)(item - (int64_t)bi * max_n);
+    const int groups = (max_n + kgroup - 1) / kgroup;
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * groups; item += gridDim.x) {
+        const int bi = (int)(item / groups);
+        const int k0 = (int)(item - (int64_t)bi * groups) * kgroup;
         const fa_block b = blocks[bi];
         const int nx = b.ncp[0], ny = b.ncp[1], nz = b.ncp[2];
-        if (k >= nz || nz > max_n) continue;
+        if (k0 >= nz || nz > max_n) continue;
+        // the block's X_x and X_y serve every k of the group
         const double *Xx = Xg + (int64_t)bi * 3 * kPinvStride;
         const double *Xy = Xx + kPinvStride;
-        for (int e = tid; e < nx * kFitR; e += kFitThreads) (&sm.Xx[0][0])[e] = Xx[e];
+        for (int e = tid; e < nx * kFitR; e += kFitThreads) {
+            const int i = e / kFitR;
+            sm.Xx[i][e - i * kFitR] = Xx[e];
+        }
         for (int e = tid; e < ny * kFitR; e += kFitThreads) {
             const int j = e / kFitR;
-            sm.XyT[e - j * kFitR][j] = Xy[e];
+            sm.Xy[j][e - j * kFitR] = Xy[e];
         }
-        const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
-        for (int e = tid; e < (int)lines; e += kFitThreads) {
-            const int x = e / r1;
-            sm.S[x][e - x * r1] = Tk[e];
+        const int k1 = min(nz, k0 + kgroup);
+        for (int k = k0; k < k1; ++k) {
+            const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
+            for (int e = tid; e < (int)lines; e += kFitThreads) {
+                const int x = e / r1;
+                sm.S[x][e - x * r1] = Tk[e];
+            }
+            __syncthreads();
+            // U (nx x r1) = X_x (nx x r0) S (r0 x r1): one strip of up to 4
+            // column tiles per row tile, sharing the A operand
+            const int mx = (nx + 15) >> 4, ny1 = (r1 + 15) >> 4, ks0 = (r0 + 3) >> 2;
+            for (int ti = wave; ti < mx; ti += kWaves) {
+                const int i = 16 * ti + lr;
+                f64x4 acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < ks0; ++ks) {
+                    const int x = 4 * ks + lk;
+                    const bool xok = x < r0;
+                    const double av = (i < nx && xok) ? sm.Xx[i][x] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int yy = 16 * q + lr;
+                        const double bv = (q < ny1 && yy < r1 && xok) ? sm.S[x][yy] : 0.0;
+                        acc[q] = mfma64(av, bv, acc[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) sm.U[16 * ti + 4 * r + lk][16 * q + lr] = acc[q][r];
+            }
+            __syncthreads();
+            // P[:, :, k] (nx x ny) = U (nx x r1) X_y^T (r1 x ny), strips as above
+            float *Pb = ctrl + b.ctrl_off;
+            const int my = (ny + 15) >> 4, ks1 = (r1 + 3) >> 2;
+            for (int ti = wave; ti < mx; ti += kWaves) {
+                const int i = 16 * ti + lr;
+                f64x4 acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < ks1; ++ks) {
+                    const int yy = 4 * ks + lk;
+                    const bool yok = yy < r1;
+                    const double av = (i < nx && yok) ? sm.U[i][yy] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 16 * q + lr;
+                        const double bv = (q < my && j < ny && yok) ? sm.Xy[j][yy] : 0.0;
+                        acc[q] = mfma64(av, bv, acc[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ii = 16 * ti + 4 * r + lk, jj = 16 * q + lr;
+                        if (ii < nx && jj < ny) Pb[((int64_t)ii * ny + jj) * nz + k] = (float)acc[q][r];
+                    }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int e = tid; e < nx * r1; e += kFitThreads) {  // U = X_x S
-            const int i = e / r1, yy = e - i * r1;
-            double acc = 0.0;
-            for (int x = 0; x < r0; ++x) acc += sm.Xx[i][x] * sm.S[x][yy];
-            sm.U[i][yy] = acc;
-        }
-        __syncthreads();
-        float *Pb = ctrl + b.ctrl_off;
-        for (int e = tid; e < nx * ny; e += kFitThreads) {  // P[:, :, k] = U X_y^T
-            const int i = e / ny, j = e - i * ny;
-            double acc = 0.0;
-            for (int yy = 0; yy < r1; ++yy) acc += sm.U[i][yy] * sm.XyT[yy][j];
-            Pb[((int64_t)i * ny + j) * nz + k] = (float)acc;
-        }
-        __syncthreads();
     }
 }
 
@@ -403,9 +492,12 @@ hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, i
     const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
     hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
                        nblocks, knots, rx, ry, rz, max_n, samples, Xg, T);
-    const int gxy = (int)std::min<int64_t>((int64_t)nblocks * max_n, 65536);
+    // k values per workgroup: as many as keep about 2048 workgroups busy
+    const int kgroup = (int)std::max<int64_t>(1, std::min<int64_t>(max_n, (int64_t)nblocks * max_n / 2048));
+    const int64_t groups = (max_n + kgroup - 1) / kgroup;
+    const int gxy = (int)std::min<int64_t>((int64_t)nblocks * groups, 65536);
     hipLaunchKernelGGL(fit_xy_kernel, dim3(gxy), dim3(kFitThreads), sizeof(FitXYSmem), s, blocks,
-                       nblocks, knots, rx, ry, max_n, Xg, T, ctrl);
+                       nblocks, knots, rx, ry, max_n, kgroup, Xg, T, ctrl);
     return hipGetLastError();
 }
 
