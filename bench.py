@@ -38,6 +38,7 @@ KERNEL_SOURCES = {
     "ncp_search": ["paper_2409_00184_amd/csrc/fa_fit.hip",
                    "paper_2409_00184_amd/csrc/fa_decode.hip",
                    "paper_2409_00184_amd/csrc/fa_device.hpp"],
+    "fit": ["paper_2409_00184_amd/csrc/fa_fit.hip", "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "fit_decode": ["paper_2409_00184_amd/csrc/fa_fit.hip",
                    "paper_2409_00184_amd/csrc/fa_adjoint.hip",
                    "paper_2409_00184_amd/csrc/fa_decode.hip",
