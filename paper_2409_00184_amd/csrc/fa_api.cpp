@@ -446,8 +446,15 @@ namespace {
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct SearchLayout {
-    int64_t desc, knots, ctrl, decoded, fitws, total, cstride;
+    int64_t desc, knots, ctrl, decoded, fitws, part, total, cstride;
 };
+
+// residual partial sums of the search: enough chunks per block to give the
+// reduction about 1024 workgroups
+int search_chunks(int32_t nblocks) {
+    const int c = (1024 + nblocks - 1) / nblocks;
+    return c < 1 ? 1 : (c > 64 ? 64 : c);
+}
 
 SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree,
                            int32_t ncp_hi) {
@@ -459,7 +466,8 @@ SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree
     L.ctrl = align_up(L.knots + 3 * (int64_t)(ncp_hi + degree + 1) * 4, 256);
     L.decoded = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
     L.fitws = align_up(L.decoded + (int64_t)nblocks * vox * 4, 256);
-    L.total = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
+    L.part = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
+    L.total = align_up(L.part + (int64_t)nblocks * search_chunks(nblocks) * 16, 256);
     return L;
 }
 
@@ -507,9 +515,13 @@ fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res
         fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, n, w + L.fitws,
                                      L.total - L.fitws, stream);
         if (st != FA_OK) return st;
-        st = fa_model_errors(desc, nblocks, knots, ctrl, FA_F32, res, samples, decoded,
-                             errs + 2 * (n - ncp_lo), 2 * (int64_t)ncand, stream);
+        st = fa_decode_blocks(desc, nblocks, knots, ctrl, FA_F32, res, 1u, nullptr, nullptr,
+                              nullptr, 0, decoded, stream);
         if (st != FA_OK) return st;
+        e = launch_residual(samples, decoded, (int64_t)res[0] * res[1] * res[2], nblocks,
+                            errs + 2 * (n - ncp_lo), 2 * (int64_t)ncand, s,
+                            search_chunks(nblocks), reinterpret_cast<double *>(w + L.part));
+        if (e != hipSuccess) return FA_ERR_DEVICE;
     }
     return FA_OK;
 }

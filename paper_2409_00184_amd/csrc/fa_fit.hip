@@ -346,14 +346,23 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
     }
 }
 
-// errs[b * stride + 0] = max |y - f|, errs[b * stride + 1] = sqrt(mean (y-f)^2)
+// errs[b * stride + 0] = max |y - f|, errs[b * stride + 1] = sqrt(mean (y-f)^2).
+// With chunks > 1 a block's voxels are split into `chunks` equal ranges,
+// each reduced by its own workgroup into part[(b * chunks + c) * 2 + {0,1}]
+// (max, sum of squares), and combine_kernel finishes the block in a fixed
+// order (deterministic either way).
 __global__ __launch_bounds__(kFitThreads) void residual_kernel(const float *y, const float *f,
                                                                 int64_t vox, int nblocks,
+                                                                int chunks, double *part,
                                                                 float *errs, int64_t stride) {
     __shared__ float smax[kFitThreads];
     __shared__ double ssum[kFitThreads];
     const int tid = threadIdx.x;
-    for (int bi = blockIdx.x; bi < nblocks; bi += gridDim.x) {
+    const int64_t cv = (vox / chunks + 3) / 4 * 4;  // voxels per chunk, a multiple of 4
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * chunks; item += gridDim.x) {
+        const int bi = (int)(item / chunks), c = (int)(item - (int64_t)bi * chunks);
+        const int64_t v0 = (int64_t)c * cv;
+        const int64_t v1 = c == chunks - 1 ? vox : (v0 + cv < vox ? v0 + cv : vox);
         const float *yb = y + (int64_t)bi * vox;
         const float *fb = f + (int64_t)bi * vox;
         float m = 0.0f;
@@ -361,14 +370,14 @@ __global__ __launch_bounds__(kFitThreads) void residual_kernel(const float *y, c
         if ((vox & 3) == 0) {
             const float4 *y4 = reinterpret_cast<const float4 *>(yb);
             const float4 *f4 = reinterpret_cast<const float4 *>(fb);
-            for (int64_t i = tid; i < vox / 4; i += kFitThreads) {
-                const float4 a = y4[i], c = f4[i];
-                const float r0 = a.x - c.x, r1 = a.y - c.y, r2 = a.z - c.z, r3 = a.w - c.w;
+            for (int64_t i = v0 / 4 + tid; i < v1 / 4; i += kFitThreads) {
+                const float4 a = y4[i], cc = f4[i];
+                const float r0 = a.x - cc.x, r1 = a.y - cc.y, r2 = a.z - cc.z, r3 = a.w - cc.w;
                 m = fmaxf(m, fmaxf(fmaxf(fabsf(r0), fabsf(r1)), fmaxf(fabsf(r2), fabsf(r3))));
                 s += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2 + (double)r3 * r3;
             }
         } else {
-            for (int64_t i = tid; i < vox; i += kFitThreads) {
+            for (int64_t i = v0 + tid; i < v1; i += kFitThreads) {
                 const float r = yb[i] - fb[i];
                 m = fmaxf(m, fabsf(r));
                 s += (double)r * r;
@@ -385,11 +394,29 @@ __global__ __launch_bounds__(kFitThreads) void residual_kernel(const float *y, c
             __syncthreads();
         }
         if (tid == 0) {
-            errs[(int64_t)bi * stride] = smax[0];
-            errs[(int64_t)bi * stride + 1] = (float)sqrt(ssum[0] / (double)vox);
+            if (chunks == 1) {
+                errs[(int64_t)bi * stride] = smax[0];
+                errs[(int64_t)bi * stride + 1] = (float)sqrt(ssum[0] / (double)vox);
+            } else {
+                part[item * 2] = (double)smax[0];
+                part[item * 2 + 1] = ssum[0];
+            }
         }
         __syncthreads();
     }
+}
+
+__global__ void combine_kernel(const double *part, int chunks, int64_t vox, int nblocks,
+                               float *errs, int64_t stride) {
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= nblocks) return;
+    double m = 0.0, s = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        m = fmax(m, part[((int64_t)bi * chunks + c) * 2]);
+        s += part[((int64_t)bi * chunks + c) * 2 + 1];
+    }
+    errs[(int64_t)bi * stride] = (float)m;
+    errs[(int64_t)bi * stride + 1] = (float)sqrt(s / (double)vox);
 }
 
 // Least-squares loss of a fit and its cotangent in one pass (the residual
@@ -502,10 +529,15 @@ hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, i
 }
 
 hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblocks, float *errs,
-                           int64_t stride, hipStream_t s) {
-    const int grid = nblocks < 65536 ? nblocks : 65536;
+                           int64_t stride, hipStream_t s, int chunks, double *part) {
+    if (chunks < 1 || !part) chunks = 1;
+    const int64_t items = (int64_t)nblocks * chunks;
+    const int grid = (int)(items < 65536 ? items : 65536);
     hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(kFitThreads), 0, s, y, f, vox, nblocks,
-                       errs, stride);
+                       chunks, part, errs, stride);
+    if (chunks > 1)
+        hipLaunchKernelGGL(combine_kernel, dim3((nblocks + 255) / 256), dim3(256), 0, s, part,
+                           chunks, vox, nblocks, errs, stride);
     return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, i
                       int rz, int max_n, const float *samples, double *T, float *ctrl,
                       hipStream_t s);
 hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblocks, float *errs,
-                           int64_t stride, hipStream_t s);
+                           int64_t stride, hipStream_t s, int chunks = 1, double *part = nullptr);
 hipError_t launch_mse_grad(const float *f, const float *y, int64_t vox, int nblocks, float scale,
                            float *grad, double *sumsq, hipStream_t s);
 hipError_t launch_candidate(fa_block *desc, float *knots, int nblocks, int n, int p,
