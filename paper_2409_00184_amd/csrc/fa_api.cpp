@@ -22,23 +22,6 @@ constexpr int kDefaultWaves = 4;
 constexpr int kDefaultRows = 8;
 constexpr int kDefaultGrid = 768;  // 256 CUs x 3 resident workgroups (LDS bound)
 
-int popcount4(uint32_t m) { return __builtin_popcount(m & 15u); }
-
-bool waves_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
-
-bool res_ok(const int32_t *res) {
-    if (!res) return false;
-    for (int a = 0; a < 3; ++a)
-        if (res[a] < 2) return false;
-    return true;
-}
-
-bool res_supported(const int32_t *res) {
-    for (int a = 0; a < 3; ++a)
-        if (res[a] > FA_MAX_RES) return false;
-    return true;
-}
-
 struct Tune {
     int rows, waves, grid, kernel, slab, store;
 };
@@ -54,6 +37,32 @@ Tune resolve(const fa_tune *t) {
         r.store = t->store;
     }
     return r;
+}
+
+// Default workgroup count: the separable VALU kernel runs persistently on
+// kDefaultGrid workgroups; the matrix-core kernel (two resident per CU, items
+// of very uneven length) runs one workgroup per item, which avoids the tail
+// of a persistent grid that does not divide the resident slots.
+int64_t default_grid(const Tune &t, int64_t items) {
+    if (t.grid > 0) return t.grid;
+    return t.kernel == 1 ? items : kDefaultGrid;
+}
+
+int popcount4(uint32_t m) { return __builtin_popcount(m & 15u); }
+
+bool waves_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
+bool res_ok(const int32_t *res) {
+    if (!res) return false;
+    for (int a = 0; a < 3; ++a)
+        if (res[a] < 2) return false;
+    return true;
+}
+
+bool res_supported(const int32_t *res) {
+    for (int a = 0; a < 3; ++a)
+        if (res[a] > FA_MAX_RES) return false;
+    return true;
 }
 
 bool tune_ok(const Tune &t) {
@@ -166,7 +175,7 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
             }
         }
     }
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, t.grid > 0 ? t.grid : kDefaultGrid));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, default_grid(t, n)));
     // longest processing time first onto the least loaded workgroup
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
@@ -229,8 +238,7 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     a.slab = t.slab;
     a.nt_store = t.store == 0;
     a.out = out;
-    int grid = work ? ngroups
-                    : (int)std::min<int64_t>(a.nitems, t.grid > 0 ? t.grid : kDefaultGrid);
+    int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
     hipError_t e;
     if (t.kernel == 1) e = launch_decode_mfma(a, t.waves, grid, (hipStream_t)stream);
     else e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
