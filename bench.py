@@ -234,7 +234,7 @@ def bench_c2(args):
         lp = {}
         for dt in ("bf16", "f16"):
             m.lattice(dt)
-            for kern, pl in (("valu", plan), ("mfma", fa.Plan(m, res, rows=4, waves=4, kernel=1))):
+            for kern, pl in (("valu", plan), ("mfma", fa.Plan(m, res, kernel=1))):
                 o2 = torch.empty_like(out)
                 g2, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dt, plan=pl, out=o2))
                 lms, lev, _ = timed_steps(g2.replay, args.steps, args.warmup, stream)
@@ -824,14 +824,20 @@ def bench_c5(args):
     nvox = b.nblocks * 64 ** 3
     out = torch.empty((b.nblocks, 4) + res, device="cuda")
     stream = torch.cuda.current_stream()
+    from paper_2409_00184_amd import autotune
+    # schedules the VALU kernel is tuned over for this uniform batch
+    cands = [(r, w, gr, 0, 8192, st) for r in (8, 16) for w in (4, 8) for gr in (768, 1 << 20)
+             for st in (0, 1)]
     variants = {}
     for name, dtype, kernel in (("f32_valu", "f32", 0), ("bf16_mfma", "bf16", 1),
                                 ("f16_mfma", "f16", 1), ("bf16_valu", "bf16", 0),
                                 ("f16_valu", "f16", 0)):
         m.lattice(dtype)
-        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1) if kernel else fa.Plan(m, res, 4, 4,
-                                                                                1 << 20, 0,
-                                                                                8192, 1)
+        if kernel:
+            plan = fa.Plan(m, res, kernel=1)
+        else:
+            plan, _ = autotune.tune(m, res, 15, dtype, candidates=cands,
+                                    use_cache=not args.retune)
         graph, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dtype, plan=plan, out=out))
         ms, ev_ms, _ = timed_steps(graph.replay, max(5, args.steps // 5), 2, stream)
         lat_b = (4 if dtype == "f32" else 2) * b.ctrl.size
@@ -900,7 +906,7 @@ def probe(args):
         b = fi.config_c5()
         m = fa.MicroModels.from_batch(b)
         m.lattice("bf16")
-        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1)
+        plan = fa.Plan(m, res, kernel=1)
         out = torch.empty((b.nblocks, 4) + res, device="cuda")
         run = lambda: fa.decode(m, res, 15, dtype="bf16", plan=plan, out=out)
     else:

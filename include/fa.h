@@ -57,6 +57,10 @@ typedef enum fa_dtype {
     FA_BF16 = 1, /* bfloat16 holding P / scale (per-block max-abs scaling) */
     FA_F16 = 2   /* IEEE half holding P / scale                             */
 } fa_dtype;
+/* 2-byte lattices are read in whole dwords: a block whose lattice has an odd
+ * number of values is read up to two bytes past its last value (values
+ * outside the block never enter a result), so the allocation must extend
+ * to the next 4-byte boundary (any hipMalloc allocation does). */
 
 /* Maximum degree and control points per axis taken by the kernels. */
 #define FA_MAX_DEGREE 3
@@ -102,7 +106,9 @@ typedef struct fa_tune {
     int32_t kernel;        /* 0 = separable VALU, 1 = separable MFMA            */
     int32_t slab_floats;   /* LDS lattice slab, 4096..16384 floats (default 8192);
                               larger lattices are staged in x chunks            */
-    int32_t store;         /* 0 = non-temporal stores, 1 = ordinary stores      */
+    int32_t store;         /* 0 = non-temporal stores, 1 = ordinary stores
+                              (separable VALU kernel; the MFMA kernel writes
+                              partial lines and always stores ordinarily)    */
 } fa_tune;
 
 const char *fa_status_string(fa_status s);

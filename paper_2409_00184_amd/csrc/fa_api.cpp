@@ -28,6 +28,7 @@ struct Tune {
 
 Tune resolve(const fa_tune *t) {
     Tune r{kDefaultRows, kDefaultWaves, 0, 0, kSlabDefault, 0};
+    if (t && t->kernel == 1) r.rows = kMfmaRows;
     if (t) {
         if (t->rows_per_item > 0) r.rows = t->rows_per_item;
         if (t->waves > 0) r.waves = t->waves;
@@ -137,8 +138,7 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
-    if (t.kernel == 1 && (t.rows != 4 || t.waves != 4 || res[2] > kWaveLanes))
-        return FA_ERR_UNSUPPORTED;
+    if (t.kernel == 1 && (t.rows != kMfmaRows || t.waves != 4)) return FA_ERR_UNSUPPORTED;
     const int nrowt = (res[1] + t.rows - 1) / t.rows;
     const int ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
     const int64_t n = (int64_t)nblocks * nrowt * ncolt;

@@ -165,6 +165,16 @@ __device__ __forceinline__ void basis_ders_rt(const float *t, int s, float u, in
     }
 }
 
+// Raw buffer resource over `bytes` bytes at a wave-uniform base (gfx9
+// word 3: 32-bit data format, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    const uint64_t v = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    void *p = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
+}
+
 // Workgroup barrier for LDS hand-offs only: orders LDS accesses around
 // s_barrier without waiting for outstanding global loads and stores (which
 // __syncthreads() would drain), so prefetches and output stores stay in

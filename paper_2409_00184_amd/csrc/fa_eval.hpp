@@ -55,16 +55,6 @@ __device__ __forceinline__ Vec<N> bload(__amdgpu_buffer_rsrc_t r, uint32_t off) 
     return v;
 }
 
-// Raw buffer resource over `bytes` bytes at a wave-uniform base (gfx9
-// word 3: 32-bit data format, no swizzle).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
-    const uint64_t v = reinterpret_cast<uint64_t>(base);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    void *p = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
-    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
-}
-
 // Knot windows and lattice rows of one block, either through buffer
 // resources (the block is the same in every lane) or through plain 64-bit
 // addresses (lanes in different blocks).
@@ -74,8 +64,11 @@ struct BlockLoads;
 template <>
 struct BlockLoads<true> {
     __amdgpu_buffer_rsrc_t kr, cr;
+    // the lattice resource ends on a dword boundary: with 2-byte values and
+    // an odd count the last value shares its dword with the next two bytes,
+    // and the hardware range check is per dword
     __device__ BlockLoads(const float *knots, uint32_t nknots, const void *ctrl, uint32_t cbytes)
-        : kr(make_rsrc(knots, nknots * 4u)), cr(make_rsrc(ctrl, cbytes)) {}
+        : kr(make_rsrc(knots, nknots * 4u)), cr(make_rsrc(ctrl, (cbytes + 3u) & ~3u)) {}
     template <int N>
     __device__ __forceinline__ Vec<N> knots(uint32_t i) const { return bload<N>(kr, i * 4u); }
     template <int N>

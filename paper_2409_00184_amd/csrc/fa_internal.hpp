@@ -13,6 +13,7 @@ constexpr int kSlabDefault = 8192;  // LDS lattice slab of the separable decode 
 constexpr int kSlabMin = 4096;      // >= NCP_y * NCP_z of any block: one x plane fits
 constexpr int kSlabMax = 16384;
 constexpr int kMaxRes = FA_MAX_RES;
+constexpr int kMfmaRows = 16;      // y rows per work item of the matrix-core decode
 
 struct DecodeLaunch {
     const fa_block *blocks;

@@ -1,32 +1,44 @@
 // Grid decode of BF16/FP16 micro-models with matrix cores (gfx950 MFMA).
 //
-// Pattern: the per-axis contractions of the tensor-product decode are dense
-// products with the basis matrices B_a (R x NCP_a, p+1 non-zeros per row),
-// so two of the three stages run as v_mfma_f32_16x16x32_{bf16,f16} with FP32
-// accumulation (K = 32 covers NCP <= 32 in one instruction; smaller NCP are
-// zero padded):
-//   x stage (MFMA):  R1_B[u][(j,k)] = sum_i Bx[u][i] P[i][j][k]   (and Dx -> R1_D)
-//   y stage (VALU):  R2_BB = sum_j By R1_B, R2_DB = sum_j By R1_D,
-//                    R2_BD = sum_j Dy R1_B        (banded, FP32, rounded once)
-//   z stage (MFMA):  value = sum_k Bz[w][k] R2_BB,  d/dw = sum_k Dz R2_BB,
-//                    d/du = sum_k Bz R2_DB,        d/dv = sum_k Bz R2_BD
-// Knot spans and basis values are computed in FP32 and rounded to the
-// input type only as MFMA operands; the stored lattice holds P / s_b and
-// the outputs are multiplied by the per-block scale s_b in FP32.
+// Pattern: for every control plane i (lattice index along x) the 2-D
+// contraction of the plane with the y and z bases,
+//     U_i[v][w] = sum_j sum_k By[v][j] P[i][j][k] Bz[w][k],
+// is a pair of dense products, both on matrix cores with FP32 accumulation:
+//     Q[j][w] = sum_k P[i][j][k] Bz[w][k]    v_mfma_f32_16x16x32 (K = NCP_z <= 32)
+//     U[w][v] = sum_j Q[j][w] By[v][j]       v_mfma_f32_16x16x16 (K = 16 y-window rows)
+// and, for the gradients, Q_D with Dz in place of Bz, U_DB = Dy Q, U_BD =
+// By Q_D.  A lane receives Q[4(l/16)+r][l%16] from the first product and
+// the second reads its A operand as A[l%16][4(l/16)+e], so Q moves from
+// the accumulators to the next product in registers, rounded once to the
+// input type (no LDS round trip).
+// The x contraction is banded (p+1 non-zero basis functions per position)
+// and runs on the VALU: each lane keeps U of the last p+1 planes for its
+// four outputs in a ring indexed by plane mod (p+1) and walks u = 0..Rx-1,
+//     value = sum Bx U_BB,  d/du = sum Dx U_BB,
+//     d/dv  = sum Bx U_DB,  d/dw = sum Bx U_BD,
+// with the x basis in FP32 from a per-item LDS table (the per-block scale
+// folded in, coefficients stored in ring order).  A new plane is produced
+// only when the span along x advances, so the matrix-core work per item is
+// NCP_x planes x 5 products per wave.
 //
-// A work item is (block, 4 consecutive y rows, up to 64 z columns); its
-// lattice slab P[:, jlo..jhi, :] is staged once in LDS transposed to
-// [(j,k)][i] so an MFMA B fragment is one 16-byte LDS read.  The x axis is
-// walked in chunks of 16 voxels; in each chunk the four waves share the x
-// stage, then the y stage, then each wave runs the z stage for 4 x voxels x
-// 4 rows and stores straight from the accumulators (16 lanes write 64
-// contiguous bytes per row, the 4 column tiles of a wave complete 256 B).
-// Items the tile does not fit (NCP > 32, or a y window wider than the LDS
-// budget) are decoded voxel by voxel by the same workgroup.
+// Rounded to the input type: the stored lattice (P / s_b), the z basis, Q
+// and the y basis.  Knot spans and every basis value are computed in FP32.
 //
-// Operand layouts of v_mfma_f32_16x16x32 (checked on the device): lane l
-// holds A[l%16][8(l/16) .. 8(l/16)+7], B[8(l/16) .. +7][l%16], and receives
-// D[4(l/16) + r][l%16], r = 0..3.
+// Work item = (block, 16 consecutive y rows, 64 z columns); wave q of the
+// four owns columns col0+16q .. col0+16q+15 and lane (g, l16) computes the
+// outputs (v = row0 + l16, w = col0 + 16q + 4g + r), r = 0..3.  Per x
+// position the four waves pass their 16 x 16 tiles through an LDS tile of
+// the item's 16 rows x 64 columns, so that every store instruction writes
+// four whole 256-byte z rows (a quarter wave per row): quarter rows stored
+// by different waves reach L2 at different times and were measured at 3.6
+// against 5.7 TB/s for whole rows.
+// Items the tile does not take (NCP_z > 32, or a y window of more than 16
+// lattice rows) are decoded voxel by voxel by the same workgroup.
+//
+// Operand layouts (checked on the device):
+//   v_mfma_f32_16x16x32: lane l holds A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], e < 8
+//   v_mfma_f32_16x16x16: lane l holds A[l%16][4(l/16)+e], B[4(l/16)+e][l%16], e < 4
+//   both: lane l receives D[4(l/16)+r][l%16], r < 4.
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -35,72 +47,120 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kRows = 4;     // y rows per item
-constexpr int kUC = 16;      // x voxels per chunk
-constexpr int kK = 32;       // MFMA K (NCP padded)
-constexpr int kPtStride = 40;  // halfs per (j,k) row of the transposed slab
-constexpr int kR2Stride = 40;  // halfs per (u,v) row of R2
-constexpr int kStageStride = 68;  // floats per staged output row (64 + 4: no bank conflicts)
+constexpr int kRows = kMfmaRows;  // y rows per item (N of the second product)
+constexpr int kK = 32;     // K of the first product: NCP_z
+constexpr int kJ = 16;     // K of the second product: y-window lattice rows
+constexpr int kCpol = 0;  // ordinary stores (measured faster than non-temporal here)
+constexpr int kStage = 32;   // control planes whose fragments LDS holds at once
 
-// FP32 -> BF16 / FP16 bits, round to nearest even (the hardware conversions
-// v_cvt_pk_bf16_f32 / v_cvt_f16_f32).
-__device__ __forceinline__ uint16_t to_bits(float x, bool bf) {
-    uint16_t r;
-    if (bf) {
-        __bf16 h = (__bf16)x;
-        __builtin_memcpy(&r, &h, 2);
+// Two FP32 values as one dword of two 16-bit values (round to nearest even).
+template <int DT>
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    uint32_t r;
+    if constexpr (DT == FA_BF16) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+        __builtin_memcpy(&r, &v, 4);
     } else {
-        _Float16 h = (_Float16)x;
-        __builtin_memcpy(&r, &h, 2);
+        typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+        const f16x2 v = {(_Float16)lo, (_Float16)hi};
+        __builtin_memcpy(&r, &v, 4);
     }
     return r;
 }
 
-__device__ __forceinline__ f32x4v mfma(const u16x8 &a, const u16x8 &b, const f32x4v &c, bool bf) {
-    if (bf) {
+template <int DT>
+__device__ __forceinline__ f32x4v mma32(const u32x4 &a, const u32x4 &b) {
+    const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (DT == FA_BF16) {
         bf16x8 x, y;
         __builtin_memcpy(&x, &a, 16);
         __builtin_memcpy(&y, &b, 16);
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, z, 0, 0, 0);
+    } else {
+        f16x8 x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, z, 0, 0, 0);
     }
-    f16x8 x, y;
-    __builtin_memcpy(&x, &a, 16);
-    __builtin_memcpy(&y, &b, 16);
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
 }
 
-struct MfmaArgs {
-    DecodeLaunch d;
-    int ncmax;  // slab columns (j,k) the LDS holds
+template <int DT>
+__device__ __forceinline__ f32x4v mma16(const u32x2 &a, const u32x2 &b) {
+    const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (DT == FA_BF16) {
+        i16x4 x, y;
+        __builtin_memcpy(&x, &a, 8);
+        __builtin_memcpy(&y, &b, 8);
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, z, 0, 0, 0);
+    } else {
+        f16x4 x, y;
+        __builtin_memcpy(&x, &a, 8);
+        __builtin_memcpy(&y, &b, 8);
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, z, 0, 0, 0);
+    }
+}
+
+// Entries [k0, k0 + 2 NW) of the dense basis row of a position whose span
+// is s (N[r] sits at lattice index s-P+r, zeros elsewhere), as NW dwords of
+// two 16-bit values.
+template <int DT, int P, int NW>
+__device__ __forceinline__ void dense_frag(const float (&N)[P + 1], int s, int k0,
+                                           uint32_t (&f)[NW]) {
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+        const int r0 = k0 + 2 * m - (s - P);
+        float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+        for (int r = 0; r <= P; ++r) {
+            lo = (r0 == r) ? N[r] : lo;
+            hi = (r0 + 1 == r) ? N[r] : hi;
+        }
+        f[m] = pack2<DT>(lo, hi);
+    }
+}
+
+// Dynamic LDS of one workgroup: the first product's A fragments of up to
+// kStage control planes (fragment of lane l of plane i at [i][l], 16 bytes),
+// the per-x-position table and the knots.
+struct MSmem {
+    u32x4 *frag;
+    f32x4v *tile;  // [channel][row 16][16 groups of 4 columns], group ^ row
+    float4 *xB;  // scale * Bx in ring order
+    float4 *xD;  // scale * Dx in ring order
+    int *xS;     // span along x
+    float *kn;
 };
 
-__host__ __device__ inline size_t mfma_lds_bytes(int ncmax) {
-    return size_t(ncmax) * kPtStride * 2        // transposed slab
-           + size_t(kUC) * (ncmax + 4) * 4 * 2  // R1_B, R1_D (FP32)
-           + size_t(kUC * kRows) * kR2Stride * 2 * 3  // R2 (16-bit)
-           + sizeof(float) * (kMaxKnotsPerBlock + 4)   // knots
-           + sizeof(float) * 9 * kRows;                 // y basis rows
+__host__ __device__ inline size_t mfma_lds_bytes(int rx) {
+    return size_t(kStage) * kWave * 16 + size_t(4 * kRows * 16) * 16 + sizeof(float4) * 2 * rx +
+           sizeof(int) * ((rx + 3) & ~3) + sizeof(float) * (kMaxKnotsPerBlock + 4);
 }
 
-// Basis row of one position (span s, degree p) as the 8 consecutive 16-bit
-// K entries [8g, 8g+8) of a dense row.
-__device__ __forceinline__ u16x8 basis_frag(const float (&N)[4], int s, int p, int g, bool bf) {
-    u16x8 f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int r = 8 * g + e - (s - p);
-        float v = 0.0f;
-#pragma unroll
-        for (int q = 0; q <= 3; ++q) v = (r == q) ? N[q] : v;
-        f[e] = to_bits(v, bf);
-    }
-    return f;
+__device__ __forceinline__ MSmem mcarve(void *base, int rx) {
+    MSmem s;
+    char *p = static_cast<char *>(base);
+    s.frag = reinterpret_cast<u32x4 *>(p);
+    p += size_t(kStage) * kWave * 16;
+    s.tile = reinterpret_cast<f32x4v *>(p);
+    p += size_t(4 * kRows * 16) * 16;
+    s.xB = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * rx;
+    s.xD = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * rx;
+    s.xS = reinterpret_cast<int *>(p);
+    p += sizeof(int) * ((rx + 3) & ~3);
+    s.kn = reinterpret_cast<float *>(p);
+    return s;
 }
 
-// Voxel-by-voxel decode of one item (items the tile does not fit).
+// Voxel-by-voxel decode of one item (items the tile does not take).
 template <int P>
 __device__ void direct_item(const DecodeLaunch &a, const fa_block &B, int b, int row0, int nrows,
                             int col0) {
@@ -149,219 +209,237 @@ __device__ void direct_item(const DecodeLaunch &a, const fa_block &B, int b, int
     }
 }
 
-__device__ void mfma_item(const MfmaArgs &A, const fa_block &B, int b, int row0, int nrows,
-                          int col0, char *lds) {
-    const DecodeLaunch &a = A.d;
-    const bool bf = a.dtype == FA_BF16;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+template <int DT, int P>
+__device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int row0, int nrows,
+                          int col0, const MSmem &sm) {
+    const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
 
-    uint16_t *Pt = reinterpret_cast<uint16_t *>(lds);
-    float *R1B = reinterpret_cast<float *>(lds + size_t(A.ncmax) * kPtStride * 2);
-    const int r1s = A.ncmax + 4;
-    float *R1D = R1B + kUC * r1s;
-    uint16_t *R2 = reinterpret_cast<uint16_t *>(R1D + kUC * r1s);
-    float *kn = reinterpret_cast<float *>(R2 + kUC * kRows * kR2Stride * 3);
-    float *ytab = kn + kMaxKnotsPerBlock + 4;  // per row: By[4], Dy[4], window start
-    const int P = B.degree[0];
-
-    lds_barrier();  // previous item done with LDS
+    lds_barrier();  // the previous item is done with the LDS table
     const int nkn = nx + ny + nz + 3 * (P + 1);
-    for (int e = tid; e < nkn; e += blockDim.x) kn[e] = a.knots[B.knot_off + e];
+    for (int e = tid; e < nkn; e += blockDim.x) sm.kn[e] = a.knots[B.knot_off + e];
     lds_barrier();
-    const float *tx = kn, *ty = tx + nx + P + 1, *tz = ty + ny + P + 1;
+    const float *tx = sm.kn, *ty = tx + nx + P + 1, *tz = ty + ny + P + 1;
 
     const int jlo = span_search(ny, P, ty, grid_pos(row0, a.ry)) - P;
     const int jhi = span_search(ny, P, ty, grid_pos(row0 + nrows - 1, a.ry));
-    const int jn = jhi - jlo + 1;
-    const int ncols = jn * nz;
-    const int nct = (ncols + 15) >> 4;
-    if (nx > kK || ny > kK || nz > kK || nct * 16 > A.ncmax || nrows > kRows) {
-        if (P == 3) direct_item<3>(a, B, b, row0, nrows, col0);
-        else if (P == 2) direct_item<2>(a, B, b, row0, nrows, col0);
-        else direct_item<1>(a, B, b, row0, nrows, col0);
+    if (nz > kK || jhi - jlo + 1 > kJ) {
+        direct_item<P>(a, B, b, row0, nrows, col0);
         return;
     }
 
-    // transposed slab Pt[(j,k)][i], zero padded to 16 columns x 32 K entries;
-    // one column per thread (consecutive threads read consecutive z points),
-    // written to LDS 8 K entries (16 bytes) at a time
-    const uint16_t *P16 = static_cast<const uint16_t *>(a.ctrl) + B.ctrl_off;
-    const int64_t pstride = (int64_t)ny * nz;
-    for (int c = tid; c < nct * 16; c += blockDim.x) {
-        const bool cv = c < ncols;
-        const int jj = cv ? c / nz : 0;
-        const uint16_t *src = P16 + (int64_t)(jlo + jj) * nz + (c - jj * nz);
+    // x table: span and scale * basis, the coefficient of plane s-P+r in
+    // ring slot (s-P+r) mod (P+1)
+    const float scale = B.scale;
+    for (int u = tid; u < a.rx; u += blockDim.x) {
+        const float pu = grid_pos(u, a.rx);
+        const int s = span_search(nx, P, tx, pu);
+        float N[P + 1], D[P + 1];
+        basis_ders<P>(tx, s, pu, N, D);
+        const int base = (s - P) % (P + 1);
+        float cb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, cd[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int i8 = 0; i8 < kK; i8 += 8) {
-            u16x8 v;
+        for (int m = 0; m <= P; ++m) {
+            const int r = (m - base + P + 1) % (P + 1);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (cv && i8 + e < nx) ? src[(i8 + e) * pstride] : 0;
-            *reinterpret_cast<u16x8 *>(Pt + c * kPtStride + i8) = v;
+            for (int t = 0; t <= P; ++t) {
+                cb[m] = r == t ? N[t] * scale : cb[m];
+                cd[m] = r == t ? D[t] * scale : cd[m];
+            }
         }
-    }
-    // R2 K padding (k >= nz) stays zero for the whole item
-    for (int e = tid; e < kUC * kRows * 3 * (kK - nz); e += blockDim.x) {
-        const int row = e / (kK - nz), k = nz + e % (kK - nz);
-        R2[row * kR2Stride + k] = 0;
+        sm.xB[u] = make_float4(cb[0], cb[1], cb[2], cb[3]);
+        sm.xD[u] = make_float4(cd[0], cd[1], cd[2], cd[3]);
+        sm.xS[u] = s;
     }
 
-    // z fragments of this lane: columns w = col0 + 16 nt + l16, K entries 8g..8g+7
-    u16x8 fBz[4], fDz[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int w = min(col0 + 16 * nt + l16, a.rz - 1);
-        const float pw = grid_pos(w, a.rz);
-        const int sw = span_search(nz, P, tz, pw);
-        float N[4], D[4];
-        basis_ders_rt(tz, sw, pw, P, N, D);
-        fBz[nt] = basis_frag(N, sw, P, g, bf);
-        fDz[nt] = basis_frag(D, sw, P, g, bf);
-    }
-    // y basis of the item's rows (FP32, for the VALU y stage) into LDS
-    if (tid < kRows) {
-        const int v = row0 + min(tid, nrows - 1);
-        const float pv = grid_pos(v, a.ry);
-        const int sv = span_search(ny, P, ty, pv);
-        float N[4], D[4];
-        basis_ders_rt(ty, sv, pv, P, N, D);
-        for (int q = 0; q < 4; ++q) {
-            ytab[tid * 9 + q] = N[q];
-            ytab[tid * 9 + 4 + q] = D[q];
-        }
-        ytab[tid * 9 + 8] = __int_as_float((sv - P - jlo) * nz);
-    }
-
-    const int64_t vox = (int64_t)a.rx * a.ry * a.rz;
-    const int64_t plane = (int64_t)a.ry * a.rz;
-    int64_t choff[4];
+    // B operand of the second product: By / Dy of row v = row0 + l16 at
+    // lattice rows jlo + 4g .. jlo + 4g + 3
+    uint32_t fBy[2], fDy[2];
     {
-        int c = 0;
+        const float pv = grid_pos(row0 + min(l16, nrows - 1), a.ry);
+        const int sv = span_search(ny, P, ty, pv);
+        float N[P + 1], D[P + 1];
+        basis_ders<P>(ty, sv, pv, N, D);
+        dense_frag<DT, P, 2>(N, sv, jlo + 4 * g, fBy);
+        dense_frag<DT, P, 2>(D, sv, jlo + 4 * g, fDy);
+    }
+    // B operand of the first product: Bz / Dz of column col0 + 16q + l16 at
+    // lattice indices 8g .. 8g + 7
+    uint32_t fBz[4], fDz[4];
+    {
+        const float pw = grid_pos(min(col0 + 16 * q + l16, a.rz - 1), a.rz);
+        const int sw = span_search(nz, P, tz, pw);
+        float N[P + 1], D[P + 1];
+        basis_ders<P>(tz, sw, pw, N, D);
+        dense_frag<DT, P, 4>(N, sw, 8 * g, fBz);
+        dense_frag<DT, P, 4>(D, sw, 8 * g, fDz);
+    }
+    const u32x4 bz = {fBz[0], fBz[1], fBz[2], fBz[3]};
+    const u32x4 dz = {fDz[0], fDz[1], fDz[2], fDz[3]};
+    const u32x2 by = {fBy[0], fBy[1]};
+    const u32x2 dy = {fDy[0], fDy[1]};
+
+    // A operand of the first product: P[i][jlo + l16][8g .. 8g + 7] through a
+    // buffer resource over this block's lattice, rounded up to whole dwords
+    // (the hardware range check is per dword; reads past the end return
+    // zero).  Entries k >= NCP_z and rows j >= NCP_y hold other lattice
+    // values or the bytes after the lattice: they are masked to zero, so
+    // only this block's values reach the product.  With NCP_z odd a row may
+    // start on a half dword: five dwords are read and realigned.
+    const __amdgpu_buffer_rsrc_t pr =
+        make_rsrc(static_cast<const uint16_t *>(a.ctrl) + B.ctrl_off,
+                  ((uint32_t)nx * (uint32_t)ny * (uint32_t)nz * 2u + 3u) & ~3u);
+    const uint32_t plane_el = (uint32_t)ny * (uint32_t)nz;
+    const uint32_t row_el = (uint32_t)(jlo + l16) * (uint32_t)nz + 8u * (uint32_t)g;
+    const bool odd = (nz & 1) != 0;
+    uint32_t keep[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int k0 = 8 * g + 2 * m;
+        keep[m] = (jlo + l16 >= ny || k0 >= nz) ? 0u : (k0 + 1 >= nz ? 0xffffu : 0xffffffffu);
+    }
+    auto load_frag = [&](int i) -> u32x4 {
+        const uint32_t el = (uint32_t)i * plane_el + row_el;
+        u32x4 r;
+        if (!odd) {
+            r = __builtin_amdgcn_raw_buffer_load_b128(pr, el * 2u, 0, 0);
+        } else {
+            const uint32_t w0 = (el * 2u) & ~3u;
+            const uint32_t sh = (el & 1u) * 2u;
+            const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(pr, w0, 0, 0);
+            const uint32_t t4 = __builtin_amdgcn_raw_buffer_load_b32(pr, w0 + 16u, 0, 0);
+            r[0] = __builtin_amdgcn_alignbyte(t[1], t[0], sh);
+            r[1] = __builtin_amdgcn_alignbyte(t[2], t[1], sh);
+            r[2] = __builtin_amdgcn_alignbyte(t[3], t[2], sh);
+            r[3] = __builtin_amdgcn_alignbyte(t4, t[3], sh);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) r[m] &= keep[m];
+        return r;
+    };
+
+    // LDS tile slots: this lane writes row l16, group 4q + g; it stores row
+    // 4q + g, group l16 (columns col0 + 4 l16 .. + 3) through a buffer
+    // resource over this block's output
+    const int wslot = l16 * 16 + ((4 * q + g) ^ l16);
+    const int srow = 4 * q + g;
+    const int rslot = srow * 16 + (l16 ^ srow);
+    const int ws = col0 + 4 * l16;
+    const bool vok = srow < nrows;
+    const bool vec = (a.rz & 3) == 0;  // 16-byte aligned groups of 4 columns
+    const uint32_t vox = (uint32_t)a.rx * (uint32_t)a.ry * (uint32_t)a.rz;
+    const __amdgpu_buffer_rsrc_t orc =
+        make_rsrc(a.out + (int64_t)b * a.nch * vox, (uint32_t)a.nch * vox * 4u);
+    const uint32_t plane_b = (uint32_t)a.ry * (uint32_t)a.rz * 4u;
+    uint32_t vo = ((uint32_t)(row0 + srow) * (uint32_t)a.rz + (uint32_t)ws) * 4u;
+    uint32_t choff[4];
+    {
+        uint32_t c = 0;
+#pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
-            choff[ch] = (int64_t)c * vox;
+            choff[ch] = c * vox * 4u;
             c += (a.mask >> ch) & 1u;
         }
     }
-    float *ob = a.out + (int64_t)b * a.nch * vox;
-    const float scale = B.scale;
-    lds_barrier();  // slab and padding visible
 
-    for (int u0 = 0; u0 < a.rx; u0 += kUC) {
-        // x stage: A = x basis rows u0..u0+15, B = slab columns
-        {
-            const int u = min(u0 + l16, a.rx - 1);
-            const float pu = grid_pos(u, a.rx);
-            const int su = span_search(nx, P, tx, pu);
-            float N[4], D[4];
-            basis_ders_rt(tx, su, pu, P, N, D);
-            const u16x8 fBx = basis_frag(N, su, P, g, bf);
-            const u16x8 fDx = basis_frag(D, su, P, g, bf);
-            for (int ct = wave; ct < nct; ct += 4) {
-                const u16x8 pf = *reinterpret_cast<const u16x8 *>(Pt + (16 * ct + l16) * kPtStride + 8 * g);
-                const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
-                const f32x4v dB = mfma(fBx, pf, z, bf);
-                const f32x4v dD = mfma(fDx, pf, z, bf);
+    f32x4v W[3][P + 1];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    R1B[(4 * g + r) * r1s + 16 * ct + l16] = dB[r];
-                    R1D[(4 * g + r) * r1s + 16 * ct + l16] = dD[r];
+    for (int m = 0; m <= P; ++m) W[0][m] = W[1][m] = W[2][m] = f32x4v{0.0f, 0.0f, 0.0f, 0.0f};
+    // fragments of planes [clo, clo + kStage) in LDS: every wave loads a
+    // quarter of the planes, every wave reads all of them; the x walk then
+    // touches no global memory but its stores (a global load in the walk
+    // would make each new plane wait for every store issued before it)
+    int clo = 0;
+    auto stage = [&](int c0) {
+        const int c1 = min(nx, c0 + kStage);
+        for (int i = c0 + q; i < c1; i += 4) sm.frag[(i - c0) * kWave + lane] = load_frag(i);
+    };
+    stage(0);
+    int top = -1;
+    lds_barrier();  // x table and fragments visible
+
+    for (int u = 0; u < a.rx; ++u) {
+        const int s = __builtin_amdgcn_readfirstlane(sm.xS[u]);
+        while (top < s) {  // uniform: the next control plane enters the ring
+            ++top;
+            if (top >= clo + kStage) {  // uniform over the workgroup
+                lds_barrier();
+                clo += kStage;
+                stage(clo);
+                lds_barrier();
+            }
+            const u32x4 cur = sm.frag[(top - clo) * kWave + lane];
+            const f32x4v qb = mma32<DT>(cur, bz);
+            const f32x4v qd = mma32<DT>(cur, dz);
+            const u32x2 ab = {pack2<DT>(qb[0], qb[1]), pack2<DT>(qb[2], qb[3])};
+            const u32x2 ad = {pack2<DT>(qd[0], qd[1]), pack2<DT>(qd[2], qd[3])};
+            const f32x4v ubb = mma16<DT>(ab, by);
+            const f32x4v udb = mma16<DT>(ab, dy);
+            const f32x4v ubd = mma16<DT>(ad, by);
+            const int slot = top % (P + 1);
+#pragma unroll
+            for (int m = 0; m <= P; ++m) {
+                if (slot == m) {
+                    W[0][m] = ubb;
+                    W[1][m] = udb;
+                    W[2][m] = ubd;
                 }
             }
         }
-        lds_barrier();
-        // y stage: (u, k) pairs over the workgroup, all rows, three channels
-        for (int e = tid; e < kUC * kK; e += blockDim.x) {
-            const int ul = e >> 5, k = e & (kK - 1);
-            if (k >= nz) continue;
-            const float *rb = R1B + ul * r1s + k;
-            const float *rd = R1D + ul * r1s + k;
+        const float4 cb4 = sm.xB[u], cd4 = sm.xD[u];
+        const float cb[4] = {cb4.x, cb4.y, cb4.z, cb4.w};
+        const float cd[4] = {cd4.x, cd4.y, cd4.z, cd4.w};
+        f32x4v o[4];
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                float bb = 0.0f, db = 0.0f, bd = 0.0f;
-                const float *yt = ytab + r * 9;
-                const int c0 = __float_as_int(yt[8]);
+        for (int r = 0; r < 4; ++r) {
+            float val = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
 #pragma unroll
-                for (int q = 0; q <= 3; ++q) {
-                    if (q > P) break;
-                    const float xb = rb[c0 + q * nz], xd = rd[c0 + q * nz];
-                    bb = fmaf(yt[q], xb, bb);
-                    db = fmaf(yt[q], xd, db);
-                    bd = fmaf(yt[4 + q], xb, bd);
-                }
-                const int row = ul * kRows + r;
-                R2[(0 * kUC * kRows + row) * kR2Stride + k] = to_bits(bb, bf);
-                R2[(1 * kUC * kRows + row) * kR2Stride + k] = to_bits(db, bf);
-                R2[(2 * kUC * kRows + row) * kR2Stride + k] = to_bits(bd, bf);
+            for (int m = 0; m <= P; ++m) {
+                val = fmaf(cb[m], W[0][m][r], val);
+                gx = fmaf(cd[m], W[0][m][r], gx);
+                gy = fmaf(cb[m], W[1][m][r], gy);
+                gz = fmaf(cb[m], W[2][m][r], gz);
             }
+            o[0][r] = val;
+            o[1][r] = gx;
+            o[2][r] = gy;
+            o[3][r] = gz;
         }
+        lds_barrier();  // every wave is done reading the previous tile
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+            if ((a.mask >> ch) & 1u) sm.tile[ch * 256 + wslot] = o[ch];
         lds_barrier();
-        // z stage: wave q owns R2 rows 16q..16q+15 = x voxels u0+4q..u0+4q+3,
-        // 4 rows.  Each channel's 4 x 4 x 64 tile goes through this wave's
-        // LDS region (the R1 buffer, dead until the next chunk) so every
-        // global store writes one whole 256-byte z row.
-        {
-            const int row = 16 * wave + l16;
-            const u16x8 aBB = *reinterpret_cast<const u16x8 *>(R2 + (0 * kUC * kRows + row) * kR2Stride + 8 * g);
-            const u16x8 aDB = *reinterpret_cast<const u16x8 *>(R2 + (1 * kUC * kRows + row) * kR2Stride + 8 * g);
-            const u16x8 aBD = *reinterpret_cast<const u16x8 *>(R2 + (2 * kUC * kRows + row) * kR2Stride + 8 * g);
-            float *stage = R1B + wave * (16 * kStageStride);
-            const int w = col0 + lane;
-            // whole 64-column tile, rows of a multiple of 4 floats: every
-            // 4-voxel group is a 16-byte aligned store
-            const bool vec_store = col0 + kWave <= a.rz && (a.rz & 3) == 0;
+        if (vok) {
+#pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (!((a.mask >> ch) & 1u)) continue;
-                const u16x8 &aa = ch == 1 ? aDB : (ch == 2 ? aBD : aBB);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    const f32x4v z = {0.0f, 0.0f, 0.0f, 0.0f};
-                    const f32x4v d = mfma(aa, ch == 3 ? fDz[nt] : fBz[nt], z, bf);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        stage[(4 * g + r) * kStageStride + 16 * nt + l16] = d[r] * scale;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int ub = u0 + 4 * wave;
-                if (vec_store) {
-                    // 16-byte non-temporal stores: a quarter-wave writes one
-                    // whole 256-byte z row
-                    float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz +
-                                col0 + 4 * l16;
-#pragma unroll
-                    for (int it = 0; it < 4; ++it) {
-                        const int rr = 4 * it + g;
-                        const f32x4 val =
-                            *reinterpret_cast<const f32x4 *>(stage + rr * kStageStride + 4 * l16);
-                        if (ub + it < a.rx && g < nrows)
-                            __builtin_nontemporal_store(
-                                val, reinterpret_cast<f32x4 *>(oc + it * plane + g * a.rz));
+                const f32x4v t = sm.tile[ch * 256 + rslot];
+                uint32_t d[4];
+                __builtin_memcpy(d, &t, 16);
+                if (vec) {
+                    if (ws < a.rz) {
+                        const u32x4 dv = {d[0], d[1], d[2], d[3]};
+                        __builtin_amdgcn_raw_buffer_store_b128(dv, orc, vo, choff[ch], kCpol);
                     }
                 } else {
-                    float *oc = ob + choff[ch] + (int64_t)ub * plane + (int64_t)row0 * a.rz + w;
-                    const bool wok = w < a.rz;
 #pragma unroll
-                    for (int rr = 0; rr < 16; ++rr) {
-                        const float val = stage[rr * kStageStride + lane];
-                        if (wok && ub + (rr >> 2) < a.rx && (rr & 3) < nrows)
-                            oc[(rr >> 2) * plane + (rr & 3) * a.rz] = val;
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        if (ws + r < a.rz)
+                            __builtin_amdgcn_raw_buffer_store_b32(d[r], orc, vo + 4u * r,
+                                                                  choff[ch], kCpol);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        lds_barrier();  // R1/R2 reused by the next chunk
+        vo += plane_b;
     }
 }
 
-__global__ __launch_bounds__(256, 2) void decode_mfma_kernel(MfmaArgs A) {
+template <int DT>
+__global__ __launch_bounds__(256) void decode_mfma_kernel(DecodeLaunch a) {
     extern __shared__ float4 dyn_lds[];
-    char *lds = reinterpret_cast<char *>(dyn_lds);
-    const DecodeLaunch &a = A.d;
+    const MSmem sm = mcarve(dyn_lds, a.rx);
     const int wg = xcd_order(blockIdx.x, gridDim.x);
     int64_t beg, end, step;
     if (a.work) {
@@ -389,32 +467,24 @@ __global__ __launch_bounds__(256, 2) void decode_mfma_kernel(MfmaArgs A) {
             nrows = min(a.rows, a.ry - row0);
             col0 = (r % a.ncolt) * kWave;
         }
-        mfma_item(A, a.blocks[b], b, row0, nrows, col0, lds);
+        const fa_block &B = a.blocks[b];
+        const int p = B.degree[0];
+        if (p == 3) mfma_item<DT, 3>(a, B, b, row0, nrows, col0, sm);
+        else if (p == 2) mfma_item<DT, 2>(a, B, b, row0, nrows, col0, sm);
+        else mfma_item<DT, 1>(a, B, b, row0, nrows, col0, sm);
     }
 }
 
 }  // namespace
 
-// The x-stage slab holds jn * NCP_z <= ncmax columns; jn of 4 consecutive
-// rows of a uniform 32-point axis is at most ceil(3*29/(R-1)) + 4.
-int mfma_ncmax(int ry) {
-    int jn = (3 * 29 + (ry - 2)) / (ry - 1) + 4;
-    jn = jn < 12 ? jn : 12;
-    return ((jn * kK + 15) / 16) * 16;
-}
-
 hipError_t launch_decode_mfma(const DecodeLaunch &d, int waves, int grid, hipStream_t s) {
-    if ((d.dtype != FA_BF16 && d.dtype != FA_F16) || d.rows != kRows || waves != 4 ||
-        d.rz > kWave)
+    if ((d.dtype != FA_BF16 && d.dtype != FA_F16) || d.rows != kRows || waves != 4)
         return hipErrorNotSupported;
-    MfmaArgs A{d, mfma_ncmax(d.ry)};
-    const size_t lds = mfma_lds_bytes(A.ncmax);
-    // raise the dynamic LDS limit once per process to the largest tile
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&decode_mfma_kernel),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mfma_lds_bytes(mfma_ncmax(2)));
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(decode_mfma_kernel, dim3(grid), dim3(256), lds, s, A);
+    const size_t lds = mfma_lds_bytes(d.rx);
+    if (d.dtype == FA_BF16)
+        hipLaunchKernelGGL(decode_mfma_kernel<FA_BF16>, dim3(grid), dim3(256), lds, s, d);
+    else
+        hipLaunchKernelGGL(decode_mfma_kernel<FA_F16>, dim3(grid), dim3(256), lds, s, d);
     return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@ Bound used (u = 2^-8 for BF16, 2^-11 for FP16, S = the oracle's
 sum |basis product| |P| of each output, which is the same for P and P/s
 up to the factor s that the kernels apply in FP32):
   VALU, 2-byte storage: only P is rounded        -> |err| <= (u + 64 u32) S
-  MFMA: P, the x basis, the y-stage result and the z basis are rounded
+  MFMA: P, the z basis, the z-stage result Q and the y basis are rounded
         (4 roundings; 6 allowed for second-order terms) -> (6 u + 64 u32) S
 """
 import numpy as np
@@ -56,7 +56,7 @@ def _bound_check(out, ref, S, c, u, what):
 def _decode_case(fa, b, res, dtype, kernel):
     m = models(b)
     if kernel == 1:
-        plan = fa.Plan(m, res, rows=4, waves=4, kernel=1)
+        plan = fa.Plan(m, res, kernel=1)
     else:
         plan = fa.Plan(m, res)
     out = fa.decode(m, res, 15, dtype=dtype, plan=plan).cpu().numpy()
@@ -97,11 +97,35 @@ def test_mfma_rejects_f32_and_bad_tiles(fa):
     b = mixed_batch(54, 3)
     m = models(b)
     with pytest.raises(fa.FAError) as e:
-        fa.decode(m, (16, 16, 16), 15, dtype="f32", plan=fa.Plan(m, (16, 16, 16), 4, 4, 0, 1))
+        fa.decode(m, (16, 16, 16), 15, dtype="f32", plan=fa.Plan(m, (16, 16, 16), kernel=1))
     assert e.value.status == 2
-    with pytest.raises(fa.FAError) as e:
-        fa.Plan(m, (16, 16, 65), 4, 4, 0, 1)
-    assert e.value.status == 2
+    for rows, waves in ((4, 4), (16, 8)):  # the tile is 16 rows x 4 waves
+        with pytest.raises(fa.FAError) as e:
+            fa.Plan(m, (16, 16, 16), rows, waves, 0, 1)
+        assert e.value.status == 2
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_mfma_wide_z_and_channel_masks(fa, dtype):
+    """z resolutions above one 64-column tile (several column items per
+    row band), odd NCP_z (lattice rows starting on half dwords) and partial
+    channel masks, against the oracle under the MFMA bound; every mask's
+    channels equal the full decode's."""
+    say("mfma wide z", dtype)
+    g = fi.rng(56)
+    ncp = [(9, 7, 31), (12, 17, 5), (5, 6, 32), (7, 9, 13)]
+    deg = [(3, 3, 3), (2, 2, 2), (1, 1, 1), (3, 3, 3)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    b = fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+    res = (9, 21, 150)
+    _decode_case(fa, b, res, dtype, 1)
+    m = models(b)
+    plan = fa.Plan(m, res, kernel=1)
+    full = fa.decode(m, res, 15, dtype=dtype, plan=plan)
+    for mask in (1, 6, 8, 13):
+        part = fa.decode(m, res, mask, dtype=dtype, plan=fa.Plan(m, res, kernel=1))
+        chans = [c for c in range(4) if (mask >> c) & 1]
+        assert torch.equal(part, full[:, chans]), mask
 
 
 def test_c5_sampled(fa):
@@ -120,7 +144,7 @@ def test_c5_sampled(fa):
     ti = torch.as_tensor(idx, device="cuda").long()
     out = torch.empty((b.nblocks, 4) + res, dtype=torch.float32, device="cuda")
     for dtype, kernel in (("f32", 0), ("bf16", 1), ("f16", 1)):
-        plan = fa.Plan(m, res, rows=4, waves=4, kernel=kernel) if kernel else fa.Plan(m, res)
+        plan = fa.Plan(m, res, kernel=kernel) if kernel else fa.Plan(m, res)
         fa.decode(m, res, 15, dtype=dtype, plan=plan, out=out)
         got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
         if dtype == "f32":

@@ -5,7 +5,8 @@ import torch
 
 import fa_inputs as fi
 import oracle
-from gpu_util import check_elementwise_bound, check_normwise, mixed_batch, models, oracle_blocks, say
+from gpu_util import (check_elementwise_bound, check_normwise, dequant, host_quantize,
+                      mixed_batch, models, oracle_blocks, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +48,37 @@ def test_query_mixed_domain(fa):
     xyz = (origin + u * extent).astype(np.float32)
     for mask in (15, 1, 0b1010):
         _query_case(fa, b, nb, origin, extent, boc, xyz, f"query mixed mask {mask}", mask)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_query_low_precision_lattices(fa, dtype):
+    """BF16/FP16 lattices (P / s_b, per-block scale): the query equals the
+    oracle on the dequantised lattice to FP32 accuracy.  Lattices with an odd
+    number of values end on a half dword; points next to each cell's far
+    corner give the last lattice value the largest weight."""
+    say("query low precision", dtype)
+    nb = (2, 2, 3)
+    g = fi.rng(33)
+    ncp = [(5, 7, 9), (6, 3, 11), (9, 9, 9), (4, 5, 7), (8, 6, 5), (3, 3, 3),
+           (7, 7, 6), (5, 9, 4), (11, 3, 5), (5, 5, 5), (13, 5, 7), (2, 3, 5)]
+    deg = [(p, p, p) for p in (3, 2, 3, 1, 2, 2, 3, 3, 2, 3, 3, 1)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    b = fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+    assert sum(int(np.prod(n)) % 2 for n in ncp) >= 6
+    boc = np.arange(12, dtype=np.int32)
+    u = g.uniform(0, 1, (30000, 3))
+    corner = 1.0 - g.uniform(0, 1e-3, (4000, 3))  # just inside the far corners
+    cells = g.integers(0, 12, 4000)
+    cidx = np.stack([cells // 6, (cells // 3) % 2, cells % 3], 1)
+    pts = np.concatenate([u * np.array(nb), cidx + corner]) / np.array(nb)
+    xyz = pts.astype(np.float32)
+    m = models(b)
+    q = fa.query(m, torch.as_tensor(xyz).cuda(), nb, (0, 0, 0), (1, 1, 1),
+                 torch.as_tensor(boc).cuda(), 15, dtype).cpu().numpy()
+    codes, scales = host_quantize(b, dtype)
+    ob = oracle_blocks(b, ctrl=dequant(b, codes, scales, dtype))
+    r, S = oracle.query_points(ob, xyz, nb, (0, 0, 0), (1, 1, 1), boc, with_abs=True)
+    check_elementwise_bound(q, r, S, 64.0, f"query {dtype}")
 
 
 def test_query_c3_blocks_rays(fa):
