@@ -15,12 +15,13 @@
 // support, then z over each k's w support, and stores the plane of G once.
 // Fixed summation order, no atomics: the result is deterministic.
 //
-// Value-only cotangents (the fit's residual) use 8-wave workgroups with a
-// third of the LDS, and split each micro-model's control planes between
-// segments: a segment owns planes [i0, i1), streams exactly the x positions
-// whose basis touches them (neighbouring segments re-read the p-plane
-// overlap) and stores only its own planes, so several segments stream at
-// once on a CU and every plane is still written by one workgroup.
+// This form serves cotangents with derivative channels; a value-only
+// cotangent (the fit's residual) goes to the matrix-core form of
+// fa_adjoint_mfma.hip.  The kernel can also split a micro-model's control
+// planes between segments: a segment owns planes [i0, i1), streams exactly
+// the x positions whose basis touches them (neighbouring segments re-read
+// the p-plane overlap) and stores only its own planes, so every plane is
+// still written by one workgroup.
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -270,34 +271,18 @@ __global__ __launch_bounds__(64 * adj_waves<DER>()) void adjoint_kernel(
 hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
                           int ry, int rz, uint32_t mask, const float *g, float *G, int /*it*/,
                           hipStream_t s) {
-    const bool der = (mask & 14u) != 0;
-    const int nch = __builtin_popcount(mask & 15u);
-    // raise the dynamic LDS limits once per process (before any graph capture)
-    static const hipError_t attr = [] {
-        hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_kernel<true>),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(AdjSmem<true>));
-        hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_kernel<false>),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(AdjSmem<false>));
-        return e1 != hipSuccess ? e1 : e2;
-    }();
+    if ((mask & 15u) == 1u)  // the value channel alone: the matrix-core form
+        return launch_adjoint_value(blocks, nblocks, knots, rx, ry, rz, g, G, s);
+    const int nch = __builtin_popcount(mask & 15u);  // derivative channels present
+    // raise the dynamic LDS limit once per process (before any graph capture)
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&adjoint_kernel<true>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(AdjSmem<true>));
     if (attr != hipSuccess) return attr;
-    if (der) {
-        const int grid = nblocks < 65536 ? nblocks : 65536;
-        hipLaunchKernelGGL((adjoint_kernel<true>), dim3(grid), dim3(64 * adj_waves<true>()),
-                           sizeof(AdjSmem<true>), s, blocks, nblocks, 1, knots, rx, ry, rz, mask,
-                           nch, g, G);
-    } else {
-        // two segments per micro-model while the batch alone would not give
-        // every CU several workgroups
-        const int nseg = nblocks < 1024 ? 2 : 1;
-        const int64_t items = (int64_t)nblocks * nseg;
-        const int grid = (int)(items < 65536 ? items : 65536);
-        hipLaunchKernelGGL((adjoint_kernel<false>), dim3(grid), dim3(64 * adj_waves<false>()),
-                           sizeof(AdjSmem<false>), s, blocks, nblocks, nseg, knots, rx, ry, rz,
-                           mask, nch, g, G);
-    }
+    const int grid = nblocks < 65536 ? nblocks : 65536;
+    hipLaunchKernelGGL((adjoint_kernel<true>), dim3(grid), dim3(64 * adj_waves<true>()),
+                       sizeof(AdjSmem<true>), s, blocks, nblocks, 1, knots, rx, ry, rz, mask, nch,
+                       g, G);
     return hipGetLastError();
 }
 

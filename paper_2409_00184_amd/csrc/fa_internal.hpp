@@ -70,6 +70,9 @@ hipError_t launch_visible(const fa_ray *rays, int64_t nrays, int samples, const 
 hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
                           int ry, int rz, uint32_t mask, const float *g, float *G, int it,
                           hipStream_t s);
+// value-channel cotangent only (mask 1), on the FP32 matrix cores
+hipError_t launch_adjoint_value(const fa_block *blocks, int nblocks, const float *knots, int rx,
+                                int ry, int rz, const float *g, float *G, hipStream_t s);
 
 int64_t fit_workspace_bytes(int nblocks, int rx, int ry, int max_n);
 hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,

@@ -26,7 +26,7 @@ def _fit_case(fa, b, y, P0, res):
     out = fa.FADecode.apply(ctrl, m, res, 1, plan)
     loss = ((out - yt) ** 2).mean()
     loss.backward()
-    return m, ctrl.grad.detach().cpu().numpy().astype(np.float64), float(loss)
+    return m, ctrl.grad.detach().cpu().numpy().astype(np.float64), float(loss.detach())
 
 
 def _oracle_grad(b, P0, y, res):
