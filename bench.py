@@ -34,6 +34,7 @@ KERNEL_SOURCES = {
     "decode_mfma": ["paper_2409_00184_amd/csrc/fa_mfma.hip",
                     "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "adjoint": ["paper_2409_00184_amd/csrc/fa_adjoint.hip",
+                "paper_2409_00184_amd/csrc/fa_adjoint_mfma.hip",
                 "paper_2409_00184_amd/csrc/fa_device.hpp"],
     "ncp_search": ["paper_2409_00184_amd/csrc/fa_fit.hip",
                    "paper_2409_00184_amd/csrc/fa_decode.hip",
