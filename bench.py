@@ -789,6 +789,15 @@ def bench_c4(args):
     ms, ev_ms, _ = timed_steps(lambda: losses.append(it()), args.steps, args.warmup, stream)
     first, last = float(losses[0]), float(losses[-1])
     ms_t = timed_steps(it_torch, args.steps, args.warmup, stream)[0]
+    # the same iteration captured into one HIP graph (capturable Adam); every
+    # replay does the whole iteration's work.  The iteration is bound by its
+    # kernels' HBM traffic, not by launches, so the graph is not faster
+    mg = fa.MicroModels.from_batch(b)
+    ctrl_g = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
+    opt_g = torch.optim.Adam([ctrl_g], lr=0.05, capturable=True)
+    graph, loss_g = fa.capture_fit_step(ctrl_g, opt_g, mg, res, yf, fa.Plan(mg, res))
+    ms_g = timed_steps(graph.replay, args.steps, args.warmup, stream)[0]
+    loss_graph = float(loss_g)
     # the two HIP kernels of an iteration, timed alone
     out = torch.empty((b.nblocks, 1) + res, device="cuda")
     gin = torch.randn_like(out)
@@ -806,6 +815,8 @@ def bench_c4(args):
                    {"roofline": _roof(nvox * 4 + lat, bev, "adjoint", "c4"),
                     "forward_decode": {"ms": fev, "GB/s": (nvox * 4 + lat) / (fev * 1e-3) / 1e9},
                     "adjoint": {"ms": bev, "GB/s": (nvox * 4 + lat) / (bev * 1e-3) / 1e9},
+                    "graph_ms_per_step": ms_g,
+                    "graph_loss_after_warmup_and_timed_replays": loss_graph,
                     "torch_composed_loss_ms_per_step": ms_t,
                     "loss_first_last": [first, last]},
                    ) | ({} if args.no_cpu_baseline else

@@ -647,6 +647,33 @@ class FAFitMSE(torch.autograd.Function):
         return gc * gl, None, None, None, None
 
 
+def capture_fit_step(ctrl, opt, models, res, y, plan=None, warmup=3):
+    """One fit iteration -- zero_grad, FAFitMSE forward (value decode and
+    fused residual/loss/cotangent), the adjoint in backward, opt.step() --
+    captured into a HIP graph, so that a fit loop is one graph launch per
+    iteration.  `opt` must be capturable (e.g. Adam(..., capturable=True));
+    `warmup` eager iterations run first on a side stream (they are real
+    steps of the fit).  Returns (graph, loss): every replay performs one
+    more iteration and overwrites the static `loss` tensor."""
+    def step():
+        opt.zero_grad(set_to_none=False)
+        loss = FAFitMSE.apply(ctrl, models, res, y, plan)
+        loss.backward()
+        opt.step()
+        return loss
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(1, warmup)):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        loss = step()
+    return g, loss
+
+
 def capture(fn, warmup=1):
     """Capture fn() (HIP calls on the current stream) into a graph; returns
     (graph, result of the captured call)."""

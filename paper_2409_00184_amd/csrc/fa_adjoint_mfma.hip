@@ -15,8 +15,10 @@
 // current slice touches in a register ring (plane i in slot i mod (p+1));
 // when the span along x advances, the plane leaving the ring is complete
 // and is stored once.  One workgroup (8 waves) per micro-model streams its
-// cotangent block once, slices double-buffered in LDS and prefetched one
-// slice ahead in registers.  Fixed summation order, no floating-point
+// cotangent block once, two x slices per step: a wave runs the same tile of
+// both slices as two independent accumulation chains, which hides each
+// other's latencies and halves the barriers per slice.  Slice pairs are
+// double-buffered in LDS and the next pair is in flight in registers.  Fixed summation order, no floating-point
 // atomics: the result is deterministic.
 //
 // Operand layout of v_mfma_f32_16x16x4f32 (checked on the device): lane l
@@ -37,11 +39,11 @@ constexpr int kAM = 64;          // res[1], res[2] and NCP_y, NCP_z limit
 // distinct banks
 constexpr int kSS = 66;
 constexpr int kTS = 80;
-constexpr int kPre = (kAM * kAM) / kAT;  // slice floats per thread
+constexpr int kPre = (kAM * kAM) / kAT;  // slice floats per thread and slice
 
 struct AmSmem {
-    float g[2][kAM * kSS];  // cotangent slices [v][w], double buffered
-    float Z[kAM * kTS];     // [v][k]
+    float g[4][kAM * kSS];  // cotangent slices [v][w]: two pairs
+    float Z[2][kAM * kTS];  // [v][k] of the pair's two slices
     float Bz[kAM * kTS];    // dense z basis [w][k]
     float By[kAM * kTS];    // dense y basis [v][j]
     float4 xB[kMaxRes];     // x basis of each slice in ring order
@@ -55,7 +57,7 @@ __device__ __forceinline__ f32x4a mma4(float a, float b, const f32x4a &c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int P>
+template <int P, int TW>
 __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, int ry, int rz,
                                 const float *g, float *G, int b, AmSmem &sm) {
     constexpr int R = P + 1;  // ring slots
@@ -120,34 +122,37 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
         const int e = tid + kAT * m;
         loff[m] = e < nslice ? (e / rz) * kSS + e % rz : -1;
     }
-    float pf[kPre];  // the next slice, in flight during the current one
-    auto fetch = [&](int u) {
+    float pf[2][kPre];  // the next pair of slices, in flight during this one
+    auto fetch = [&](int u, float(&f)[kPre]) {
 #pragma unroll
         for (int m = 0; m < kPre; ++m) {
             const int e = tid + kAT * m;
-            pf[m] = (u < rx && e < nslice) ? gb[(int64_t)u * nslice + e] : 0.0f;
+            f[m] = (u < rx && e < nslice) ? gb[(int64_t)u * nslice + e] : 0.0f;
         }
     };
-    auto put = [&](int buf) {
+    auto put = [&](int buf, const float(&f)[kPre]) {
 #pragma unroll
         for (int m = 0; m < kPre; ++m)
-            if (loff[m] >= 0) sm.g[buf][loff[m]] = pf[m];
+            if (loff[m] >= 0) sm.g[buf][loff[m]] = f[m];
     };
-    fetch(0);
-    put(0);
-    fetch(1);
+    fetch(0, pf[0]);
+    fetch(1, pf[1]);
+    put(0, pf[0]);
+    put(1, pf[1]);
+    fetch(2, pf[0]);
+    fetch(3, pf[1]);
 
-    // the Y tiles of this wave (at most two) and their rings
+    // the Y tiles of this wave (at most TW) and their rings
     const int ntiles = njt * nkt;
-    f32x4a ring[2][R];
+    f32x4a ring[TW][R];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < TW; ++t)
 #pragma unroll
         for (int m = 0; m < R; ++m) ring[t][m] = f32x4a{0.0f, 0.0f, 0.0f, 0.0f};
     float *Gb = G + B.ctrl_off;
     auto store_plane = [&](int i, int slot) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < TW; ++t) {
             const int tt = wave + kAW * t;
             if (tt >= ntiles) continue;
             const int mt = tt % njt, nt = tt / njt;
@@ -168,23 +173,9 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
 
     lds_barrier();  // first slice, tile ranges visible
 
-    for (int u = 0; u < rx; ++u) {
-        const int cur = u & 1;
-        // z: Z tiles (16 v x 16 k) of slice u
-        for (int t = wave; t < nvt * nkt; t += kAW) {
-            const int mt = t % nvt, nt = t / nvt;
-            const float *ga = sm.g[cur] + (16 * mt + l16) * kSS + gq;
-            const float *bz = sm.Bz + gq * kTS + 16 * nt + l16;
-            // K steps of 4 positions covering the tile's band (none if empty)
-            f32x4a acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int st = sm.tw[0][nt] >> 2; st <= (sm.tw[1][nt] >> 2); ++st)
-                acc = mma4(ga[4 * st], bz[4 * st * kTS], acc);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sm.Z[(16 * mt + 4 * gq + r) * kTS + 16 * nt + l16] = acc[r];
-        }
-        lds_barrier();
-        // y: Y tiles (16 j x 16 k), then x: into the rings
+    // x contraction of one slice's Y tiles: advance the rings to its span,
+    // then add its contributions to the p+1 planes it touches
+    auto accumulate = [&](int u, const f32x4a (&y)[TW]) {
         const int s = __builtin_amdgcn_readfirstlane(sm.xS[u]);
         while (top < s) {  // uniform: plane top+1 enters, plane top-P leaves
             ++top;
@@ -193,25 +184,65 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
         const float4 cx = sm.xB[u];
         const float c[4] = {cx.x, cx.y, cx.z, cx.w};
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < TW; ++t) {
+            if (wave + kAW * t >= ntiles) continue;
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ring[t][m][r] = fmaf(c[m], y[t][r], ring[t][m][r]);
+        }
+    };
+
+    for (int u = 0; u < rx; u += 2) {
+        const int b0 = 2 * ((u >> 1) & 1);  // buffers of slices u, u+1
+        const bool two = u + 1 < rx;
+        // z: Z tiles (16 v x 16 k) of both slices, two chains per wave
+        for (int t = wave; t < nvt * nkt; t += kAW) {
+            const int mt = t % nvt, nt = t / nvt;
+            const int ao = (16 * mt + l16) * kSS + gq;
+            const float *ga0 = sm.g[b0] + ao, *ga1 = sm.g[b0 + 1] + ao;
+            const float *bz = sm.Bz + gq * kTS + 16 * nt + l16;
+            // K steps of 4 positions covering the tile's band (none if empty)
+            f32x4a z0 = {0.0f, 0.0f, 0.0f, 0.0f}, z1 = z0;
+            for (int st = sm.tw[0][nt] >> 2; st <= (sm.tw[1][nt] >> 2); ++st) {
+                const float bb = bz[4 * st * kTS];
+                z0 = mma4(ga0[4 * st], bb, z0);
+                z1 = mma4(ga1[4 * st], bb, z1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int zo = (16 * mt + 4 * gq + r) * kTS + 16 * nt + l16;
+                sm.Z[0][zo] = z0[r];
+                sm.Z[1][zo] = z1[r];
+            }
+        }
+        lds_barrier();
+        // y: Y tiles (16 j x 16 k) of both slices, then x for slice u, u+1
+        f32x4a y0[TW], y1[TW];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            y0[t] = y1[t] = f32x4a{0.0f, 0.0f, 0.0f, 0.0f};
             const int tt = wave + kAW * t;
             if (tt >= ntiles) continue;
             const int mt = tt % njt, nt = tt / njt;
             const float *by = sm.By + gq * kTS + 16 * mt + l16;
-            const float *zb = sm.Z + gq * kTS + 16 * nt + l16;
-            f32x4a acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int st = sm.tv[0][mt] >> 2; st <= (sm.tv[1][mt] >> 2); ++st)
-                acc = mma4(by[4 * st * kTS], zb[4 * st * kTS], acc);
-#pragma unroll
-            for (int m = 0; m < R; ++m)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ring[t][m][r] = fmaf(c[m], acc[r], ring[t][m][r]);
+            const int zo = gq * kTS + 16 * nt + l16;
+            for (int st = sm.tv[0][mt] >> 2; st <= (sm.tv[1][mt] >> 2); ++st) {
+                const float aa = by[4 * st * kTS];
+                y0[t] = mma4(aa, sm.Z[0][zo + 4 * st * kTS], y0[t]);
+                y1[t] = mma4(aa, sm.Z[1][zo + 4 * st * kTS], y1[t]);
+            }
         }
-        // slice u+1 (loaded while this slice was contracted) into the other
-        // buffer, slice u+2 into flight; the registers are written only by
-        // the loads, so waiting for them never waits for the newer ones
-        put(cur ^ 1);
-        fetch(u + 2);
+        accumulate(u, y0);
+        if (two) accumulate(u + 1, y1);
+        // slices u+2, u+3 (loaded while this pair was contracted) into the
+        // other pair of buffers, u+4, u+5 into flight; the registers are
+        // written only by the loads, so waiting for them never waits for
+        // the newer ones
+        put(b0 ^ 2, pf[0]);
+        put((b0 ^ 2) + 1, pf[1]);
+        fetch(u + 4, pf[0]);
+        fetch(u + 5, pf[1]);
         lds_barrier();
     }
     // planes still in the rings, then planes no slice touches (zero)
@@ -220,20 +251,27 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
         Gb[(int64_t)(top + 1) * ny * nz + e] = 0.0f;
 }
 
+// TW: Y tiles per wave.  Blocks with at most kAW tiles (NCP_y, NCP_z <= 32
+// for the usual shapes) run in the TW = 1 kernel, the others in the TW = 2
+// kernel; each kernel skips the other's blocks (one register budget per
+// kernel: the second tile's rings would halve the first's headroom).
+template <int TW>
 __global__ __launch_bounds__(kAT) void adjoint_value_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int rx, int ry,
                                                              int rz, const float *g, float *G) {
     extern __shared__ float4 dyn_lds[];
     AmSmem &sm = *reinterpret_cast<AmSmem *>(dyn_lds);
     // slice rows and columns outside ry x rz are never loaded: zero them once
-    for (int e = threadIdx.x; e < 2 * kAM * kSS; e += kAT) (&sm.g[0][0])[e] = 0.0f;
+    for (int e = threadIdx.x; e < 4 * kAM * kSS; e += kAT) (&sm.g[0][0])[e] = 0.0f;
     for (int it = xcd_order(blockIdx.x, gridDim.x); it < nblocks; it += gridDim.x) {
         lds_barrier();  // the previous block is done with the LDS
         const fa_block &B = blocks[it];
+        const int tiles = ((B.ncp[1] + 15) >> 4) * ((B.ncp[2] + 15) >> 4);
+        if ((tiles > kAW) != (TW == 2)) continue;  // uniform: the other kernel's block
         const int p = B.degree[0];
-        if (p == 3) adj_value_block<3>(B, knots, rx, ry, rz, g, G, it, sm);
-        else if (p == 2) adj_value_block<2>(B, knots, rx, ry, rz, g, G, it, sm);
-        else adj_value_block<1>(B, knots, rx, ry, rz, g, G, it, sm);
+        if (p == 3) adj_value_block<3, TW>(B, knots, rx, ry, rz, g, G, it, sm);
+        else if (p == 2) adj_value_block<2, TW>(B, knots, rx, ry, rz, g, G, it, sm);
+        else adj_value_block<1, TW>(B, knots, rx, ry, rz, g, G, it, sm);
     }
 }
 
@@ -242,13 +280,21 @@ __global__ __launch_bounds__(kAT) void adjoint_value_kernel(const fa_block *bloc
 hipError_t launch_adjoint_value(const fa_block *blocks, int nblocks, const float *knots, int rx,
                                 int ry, int rz, const float *g, float *G, hipStream_t s) {
     if (ry > kAM || rz > kAM) return hipErrorNotSupported;
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&adjoint_value_kernel),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(AmSmem));
+    static const hipError_t attr = [] {
+        hipError_t e1 = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&adjoint_value_kernel<1>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(AmSmem));
+        hipError_t e2 = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&adjoint_value_kernel<2>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(AmSmem));
+        return e1 != hipSuccess ? e1 : e2;
+    }();
     if (attr != hipSuccess) return attr;
     const int grid = nblocks < 65536 ? nblocks : 65536;
-    hipLaunchKernelGGL(adjoint_value_kernel, dim3(grid), dim3(kAT), sizeof(AmSmem), s, blocks,
-                       nblocks, knots, rx, ry, rz, g, G);
+    hipLaunchKernelGGL(adjoint_value_kernel<1>, dim3(grid), dim3(kAT), sizeof(AmSmem), s,
+                       blocks, nblocks, knots, rx, ry, rz, g, G);
+    hipLaunchKernelGGL(adjoint_value_kernel<2>, dim3(grid), dim3(kAT), sizeof(AmSmem), s,
+                       blocks, nblocks, knots, rx, ry, rz, g, G);
     return hipGetLastError();
 }
 

@@ -177,6 +177,50 @@ def test_graph_replay_matches_eager(fa):
         _ = (out * 2).sum().item()  # eager work between replays
 
 
+def test_captured_fit_step_matches_eager(fa):
+    """A whole fit iteration (decode, fused MSE, adjoint, capturable Adam)
+    captured into one graph: every replay, with eager work and
+    synchronisation in between, moves the lattice exactly as an eager
+    iteration from the same state does."""
+    say("captured fit step")
+    b = mixed_batch(64, 6, ncp_lo=4, ncp_hi=14)
+    res = (24, 20, 28)
+    g = fi.rng(65)
+    y = torch.as_tensor(g.normal(size=(b.nblocks,) + res).astype(np.float32)).cuda()
+    P0 = torch.as_tensor(0.1 * g.normal(size=b.ctrl.size).astype(np.float32)).cuda()
+    runs = []
+    for _ in range(2):
+        m = models(b)
+        ctrl = P0.clone().requires_grad_(True)
+        opt = torch.optim.Adam([ctrl], lr=0.05, capturable=True)
+        runs.append((m, ctrl, opt, fa.Plan(m, res)))
+    me, ce, oe, pe = runs[0]
+    mg, cg, og, pg = runs[1]
+
+    def eager():
+        oe.zero_grad(set_to_none=False)
+        loss = fa.FAFitMSE.apply(ce, me, res, y, pe)
+        loss.backward()
+        oe.step()
+        return loss
+
+    graph, loss_g = fa.capture_fit_step(cg, og, mg, res, y, pg, warmup=3)
+    for _ in range(3):  # the capture's eager warm-up iterations
+        eager()
+    torch.cuda.synchronize()
+    assert torch.equal(cg.detach(), ce.detach())
+    for rep in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        le = eager()
+        torch.cuda.synchronize()
+        d = (cg.detach() - ce.detach()).abs().max().item()
+        say("  replay", rep, "loss", float(loss_g), float(le), "max |ctrl diff|", d)
+        assert torch.equal(cg.detach(), ce.detach()), ("ctrl", rep, d)
+        assert float(loss_g) == float(le), ("loss", rep)
+        _ = (ce.detach() * 2).sum().item()  # eager work between replays
+
+
 def test_autotune_picks_valid_schedule(fa, tmp_path, monkeypatch):
     say("autotune")
     from paper_2409_00184_amd import autotune
