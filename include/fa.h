@@ -103,7 +103,9 @@ typedef struct fa_tune {
     int32_t rows_per_item; /* y rows per work item, 1..64 (default 8)           */
     int32_t waves;         /* waves (64 lanes) per workgroup: 1, 2, 4, 8        */
     int32_t grid;          /* persistent workgroups (capped at the item count)  */
-    int32_t kernel;        /* 0 = separable VALU, 1 = separable MFMA            */
+    int32_t kernel;        /* 0 = separable VALU, 1 = MFMA (BF16/FP16 lattices;
+                              16 rows x 64 columns per item and 4 waves: pass
+                              rows_per_item 0 or 16 and waves 0 or 4)       */
     int32_t slab_floats;   /* LDS lattice slab, 4096..16384 floats (default 8192);
                               larger lattices are staged in x chunks            */
     int32_t store;         /* 0 = non-temporal stores, 1 = ordinary stores
@@ -160,8 +162,8 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
  *           the same tune and res, or both NULL for the default order
  *   ngroups workgroups in the plan (ignored when work is NULL)
  *   out     device FP32 [nblocks][popcount(mask)][res0][res1][res2]
- * FA_ERR_UNSUPPORTED if tune->kernel selects the MFMA kernel with a
- * dtype or degree it does not take.
+ * FA_ERR_UNSUPPORTED if tune->kernel selects the MFMA kernel with an FP32
+ * lattice or with a tile other than 16 rows and 4 waves.
  */
 fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
                            const void *ctrl, fa_dtype dtype, const int32_t res[3],
@@ -272,7 +274,9 @@ fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t 
 /*
  * Adjoint of the grid decode (row a7): grad_ctrl = B^T grad_out, where B
  * is the linear map ctrl -> decode output of fa_decode_blocks for the same
- * blocks, res and mask.  Deterministic (no atomics).
+ * blocks, res and mask.  Deterministic (fixed summation order, no
+ * floating-point atomics).  A value-only cotangent (mask 1) runs on the
+ * FP32 matrix cores, others on the VALU.
  *   grad_out   device FP32 [nblocks][popcount(mask)][res0][res1][res2]
  *   grad_ctrl  device FP32 lattice layout (same offsets as ctrl); the
  *              lattices of the blocks are overwritten, other elements are

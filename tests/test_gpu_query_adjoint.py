@@ -162,6 +162,30 @@ def test_adjoint_vs_oracle(fa, mask, res):
         assert err <= 1e-5 * np.abs(Gr[o:o + k]).max(), (bb, err)
 
 
+@pytest.mark.parametrize("res", [(19, 64, 64), (33, 37, 50)])
+def test_adjoint_wide_lattices_vs_oracle(fa, res):
+    """Value cotangents of lattices with NCP_y or NCP_z above 32 (more than
+    eight 16 x 16 output tiles: the two-tile matrix-core kernel) next to
+    narrow ones (the one-tile kernel) in one batch, and NCP_x above the x
+    resolution (several control planes complete per x slice)."""
+    say("adjoint wide", res)
+    g = fi.rng(45)
+    ncp = [(8, 40, 36), (6, 33, 20), (5, 10, 64), (12, 24, 24), (40, 12, 8), (7, 64, 33)]
+    deg = [(3, 3, 3), (2, 2, 2), (1, 1, 1), (3, 3, 3), (2, 2, 2), (3, 3, 3)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    b = fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+    m = models(b)
+    gt = torch.randn((b.nblocks, 1) + res, generator=torch.Generator().manual_seed(46))
+    G = fa.decode_backward(m, res, gt.cuda().contiguous(), 1).cpu().numpy()
+    Gr = oracle.decode_adjoint(oracle_blocks(b), res, gt.numpy().astype(np.float64), 1)
+    for bb in range(b.nblocks):
+        o = int(b.ctrl_off[bb])
+        k = int(np.prod(b.ncp[bb]))
+        err = np.abs(G[o:o + k] - Gr[o:o + k]).max()
+        say("  block", ncp[bb], "err / scale", err / np.abs(Gr[o:o + k]).max())
+        assert err <= 1e-5 * np.abs(Gr[o:o + k]).max(), (bb, err)
+
+
 def test_adjoint_dot_product(fa):
     """<B P, g> = <P, B^T g> with the GPU forward and the GPU adjoint."""
     say("adjoint dot")
