@@ -361,6 +361,31 @@ fa_status fa_model_errors(const fa_block *blocks, int32_t nblocks, const float *
 fa_status fa_mse_grad(const float *decoded, const float *samples, int32_t nblocks, int64_t vox,
                       float grad_scale, float *grad, double *sumsq, void *stream);
 
+/*
+ * The value decode of fa_decode_blocks fused with fa_mse_grad: for every
+ * block b and voxel v, with f the value decode (mask 1) of the FP32 lattice,
+ *   grad[b][v] = grad_scale * (f[b][v] - samples[b][v]),
+ *   sumsq[b]   = sum_v (f - samples)^2   (FP64, fixed order),
+ * in one pass that reads the samples and writes grad (f itself is never
+ * stored).  grad equals fa_decode_blocks + fa_mse_grad bit for bit; sumsq
+ * differs only in the order of its FP64 sum.  Runs the separable VALU
+ * kernel (tune->kernel must be 0); tune, work, wg_off, ngroups as in
+ * fa_decode_blocks.
+ *   samples, grad  device FP32 [nblocks][res0][res1][res2]
+ *   sumsq          device FP64 [nblocks]
+ *   workspace      device, fa_decode_residual_workspace(...) bytes (one
+ *                  FP64 partial sum per work item)
+ * FA_ERR_INVALID_ARG as fa_decode_blocks, for a non-finite grad_scale or a
+ * small workspace; FA_ERR_UNSUPPORTED for the MFMA kernel.
+ */
+int64_t fa_decode_residual_workspace(int32_t nblocks, const int32_t res[3], const fa_tune *tune);
+fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const float *knots,
+                             const float *ctrl, const int32_t res[3], const fa_tune *tune,
+                             const fa_work *work, const int32_t *wg_off, int32_t ngroups,
+                             const float *samples, float grad_scale, float *grad,
+                             double *sumsq, void *workspace, int64_t workspace_bytes,
+                             void *stream);
+
 /* Bytes of device workspace fa_ncp_search needs (-1 for invalid sizes). */
 int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t degree,
                                 int32_t ncp_hi);

@@ -103,6 +103,11 @@ def _load():
                                  vp, vp, vp, vp]
     L.fa_mse_grad.restype = ctypes.c_int
     L.fa_mse_grad.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, vp]
+    L.fa_decode_residual_workspace.restype = i64
+    L.fa_decode_residual_workspace.argtypes = [i32, vp, vp]
+    L.fa_decode_residual.restype = ctypes.c_int
+    L.fa_decode_residual.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, ctypes.c_float,
+                                     vp, vp, vp, i64, vp]
     L.fa_fit_workspace.restype = i64
     L.fa_fit_workspace.argtypes = [i32, vp, i32]
     L.fa_fit_blocks.restype = ctypes.c_int
@@ -621,23 +626,51 @@ class FADecode(torch.autograd.Function):
         return gc, None, None, None, None
 
 
+def decode_residual(models, res, samples, grad_scale, plan=None, tune=None, grad=None,
+                    sumsq=None, workspace=None, stream=None):
+    """Value decode fused with the fit's residual (fa_decode_residual):
+    returns (grad, sumsq) with grad = grad_scale (f - samples) [nb, *res]
+    and sumsq[b] = sum (f - samples)^2 (FP64), f never stored."""
+    res3 = _i32x3(res)
+    if plan is not None:
+        assert plan.res == tuple(int(r) for r in res)
+        t, work, off, ng = plan.tune, _ptr(plan.work), _ptr(plan.wg_off), plan.ngroups
+    else:
+        t = tune if tune is not None else FATune(0, 0, 0, 0, 0, 0)
+        work, off, ng = None, None, 0
+    need = lib.fa_decode_residual_workspace(models.nblocks, res3, ctypes.byref(t))
+    if need < 0:
+        raise FAError("fa_decode_residual_workspace", 1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(int(need), 8), dtype=torch.uint8, device=models.device)
+    if grad is None:
+        grad = torch.empty((models.nblocks,) + tuple(int(r) for r in res), dtype=torch.float32,
+                           device=models.device)
+    if sumsq is None:
+        sumsq = torch.empty(models.nblocks, dtype=torch.float64, device=models.device)
+    assert samples.dtype == torch.float32 and samples.is_contiguous()
+    st = lib.fa_decode_residual(_ptr(models.desc), models.nblocks, _ptr(models.knots),
+                                _ptr(models.ctrl), res3, ctypes.byref(t), work, off, ng,
+                                _ptr(samples), float(grad_scale), _ptr(grad), _ptr(sumsq),
+                                _ptr(workspace), int(workspace.numel()), _stream(stream))
+    _check("fa_decode_residual", st)
+    return grad, sumsq
+
+
 class FAFitMSE(torch.autograd.Function):
-    """Loss = mean over all voxels of (B(ctrl) - y)^2 in three HIP launches:
-    value decode, fused residual / loss / cotangent (fa_mse_grad), and in
+    """Loss = mean over all voxels of (B(ctrl) - y)^2 in two HIP passes: the
+    value decode fused with the residual, loss and cotangent
+    (fa_decode_residual; the decoded values are never stored), and in
     backward the adjoint B^T of the cotangent.  y: [nblocks, *res] float32."""
 
     @staticmethod
     def forward(ctx, ctrl, models, res, y, plan):
         models.set_ctrl(ctrl.detach())
-        f = decode(models, res, 1, plan=plan)
         nvox = int(np.prod(res))
         m_all = models.nblocks * nvox
-        sumsq = torch.empty(models.nblocks, dtype=torch.float64, device=models.device)
-        st = lib.fa_mse_grad(_ptr(f), _ptr(y), models.nblocks, nvox, 2.0 / m_all, _ptr(f),
-                             _ptr(sumsq), _stream())
-        _check("fa_mse_grad", st)
+        g, sumsq = decode_residual(models, res, y, 2.0 / m_all, plan=plan)
         ctx.models, ctx.res = models, res
-        ctx.save_for_backward(f)  # now holds the cotangent 2 (f - y) / M
+        ctx.save_for_backward(g)  # the cotangent 2 (f - y) / M
         return (sumsq.sum() / m_all).to(torch.float32)
 
     @staticmethod

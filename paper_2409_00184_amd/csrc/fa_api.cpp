@@ -246,6 +246,61 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
+int64_t fa_decode_residual_workspace(int32_t nblocks, const int32_t res[3], const fa_tune *tune) {
+    if (nblocks <= 0 || !res_ok(res) || !res_supported(res)) return -1;
+    const Tune t = resolve(tune);
+    if (!tune_ok(t)) return -1;
+    const int64_t per = (int64_t)((res[1] + t.rows - 1) / t.rows) * ((res[2] + kWaveLanes - 1) / kWaveLanes);
+    return (int64_t)nblocks * per * (int64_t)sizeof(double);
+}
+
+fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const float *knots,
+                             const float *ctrl, const int32_t res[3], const fa_tune *tune,
+                             const fa_work *work, const int32_t *wg_off, int32_t ngroups,
+                             const float *samples, float grad_scale, float *grad,
+                             double *sumsq, void *workspace, int64_t workspace_bytes,
+                             void *stream) {
+    if (!blocks || !knots || !ctrl || !samples || !grad || !sumsq || !workspace ||
+        nblocks <= 0 || !res_ok(res) || !std::isfinite(grad_scale))
+        return FA_ERR_INVALID_ARG;
+    if ((work == nullptr) != (wg_off == nullptr)) return FA_ERR_INVALID_ARG;
+    if (work && ngroups <= 0) return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    const Tune t = resolve(tune);
+    if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
+    if (t.kernel != 0) return FA_ERR_UNSUPPORTED;
+    const int64_t need = fa_decode_residual_workspace(nblocks, res, tune);
+    if (need < 0 || workspace_bytes < need) return FA_ERR_INVALID_ARG;
+    DecodeLaunch a{};
+    a.blocks = blocks;
+    a.knots = knots;
+    a.ctrl = ctrl;
+    a.dtype = FA_F32;
+    a.rx = res[0];
+    a.ry = res[1];
+    a.rz = res[2];
+    a.mask = 1u;
+    a.nch = 1;
+    a.work = work;
+    a.wg_off = wg_off;
+    a.rows = t.rows;
+    a.nrowt = (res[1] + t.rows - 1) / t.rows;
+    a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
+    a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
+    a.slab = t.slab;
+    a.nt_store = t.store == 0;
+    a.out = grad;
+    a.samples = samples;
+    a.gscale = grad_scale;
+    a.partials = static_cast<double *>(workspace);
+    const int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
+    hipError_t e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_residual_combine(a.partials, nblocks, a.nrowt * a.ncolt, sumsq,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 fa_status fa_decode_blocks_plain(const fa_block *blocks, int32_t nblocks, const float *knots,
                                  const float *ctrl, const int32_t res[3], uint32_t mask,
                                  float *out, void *stream) {

@@ -18,9 +18,20 @@
 //   workgroup runs the items a host plan assigned to it, or a grid-stride
 //   share of the default order.
 //
+// The residual form (RESID) decodes the value channel only and, instead of
+//   the value f, stores gscale * (f - samples) for a fit's loss, summing
+//   (f - samples)^2 in FP64 per lane (x order), per wave (fixed shuffle
+//   tree) and per work item (waves in order) into one partial per item; a
+//   second kernel adds each block's partials in item order.  The samples
+//   are read one x position ahead through a buffer resource, and dead lanes
+//   load and store at an offset outside every resource (no branch), so the
+//   x walk issues a fixed number of memory operations per step.
+//
 // decode_plain: the baseline -- one thread per voxel, one launch per block,
 //   each thread doing its own span searches, basis evaluation and (p+1)^3
 //   window sum straight from global memory.
+#include <type_traits>
+
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -72,8 +83,8 @@ __device__ __forceinline__ float comp(const float4 &v, int r) {
     return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
 }
 
-template <int P, bool NT>
-__device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0,
+template <int P, bool NT, bool RESID>
+__device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0, int64_t item,
                          SepSmem &sm) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
@@ -148,6 +159,15 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         }
     }
 
+    // residual form: samples and cotangent of this block through buffer
+    // resources (value channel only, so both have the layout [u][v][w])
+    constexpr uint32_t kDead = 0xfffffff0u;  // beyond every resource
+    double acc = 0.0;
+    const __amdgpu_buffer_rsrc_t yr =
+        make_rsrc(RESID ? a.samples + (int64_t)b * vox : a.out, RESID ? (uint32_t)vox * 4u : 0u);
+    const __amdgpu_buffer_rsrc_t gr =
+        make_rsrc(a.out + (int64_t)b * vox, RESID ? (uint32_t)vox * 4u : 0u);
+
     for (int rb = 0; rb < nrows; rb += nwaves) {
         const int rr = rb + wave;
         const bool rok = rr < nrows;
@@ -158,8 +178,17 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         basis_ders<P>(ty, sy, yv, yB, yD);
         const int jrow = sy - P - jlo;
 
-        int clo = 0, chi = ic;
-        if (!single) {
+        float *ob = a.out + (int64_t)b * a.nch * vox + (int64_t)v * a.rz + w;
+        const bool live = rok && wok;
+        const uint32_t col_off = ((uint32_t)v * (uint32_t)a.rz + (uint32_t)w) * 4u;
+        const uint32_t pstep = (uint32_t)plane_out * 4u;
+
+      // the x walk, specialised on whether the slab holds every control
+      // plane (then it stages nothing inside the walk)
+      auto walk = [&](auto single_c) {
+        constexpr bool SINGLE = decltype(single_c)::value;
+        int clo = 0, chi = SINGLE ? nx : ic;
+        if (!SINGLE) {
             lds_barrier();
             stage(0, ic);
             lds_barrier();
@@ -169,14 +198,33 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
 #pragma unroll
         for (int r = 0; r <= P; ++r) wBB[r] = wDB[r] = wBD[r] = 0.0f;
         int top = -1;
-        float *ob = a.out + (int64_t)b * a.nch * vox + (int64_t)v * a.rz + w;
-        const bool live = rok && wok;
+        // residual form: the sample of x position u, loaded two positions
+        // ahead into one of two registers used alternately (no register
+        // copy waits for a load in flight)
+        auto yload = [&](int u) {
+            return RESID ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                         yr, (live && u < a.rx)
+                                                                 ? col_off + (uint32_t)u * pstep
+                                                                 : kDead,
+                                                         0, 0))
+                         : 0.0f;
+        };
+        // issue order load, store, load, store as in every step, so the
+        // counter wait at a step is the same on entry as in the loop (the
+        // stores go beyond the resource and are dropped)
+        auto ydummy = [&]() {
+            if (RESID) __builtin_amdgcn_raw_buffer_store_b32(0u, gr, kDead, 0, 0);
+        };
+        float y0 = yload(0);
+        ydummy();
+        float y1 = yload(1);
+        ydummy();
 
-        for (int u = 0; u < a.rx; ++u) {
+        auto step = [&](int u, float &ycur) {
             const int s = sm.xS[u];
             while (top < s) {  // uniform over the workgroup
                 ++top;
-                if (top >= chi) {
+                if (!SINGLE && top >= chi) {
                     lds_barrier();
                     clo = chi;
                     chi = min(clo + ic, nx);
@@ -225,7 +273,17 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
                 gy = fmaf(cb, wDB[r], gy);
                 gz = fmaf(cb, wBD[r], gz);
             }
-            if (live) {
+            if (RESID) {
+                // use the sample before the register is reloaded, so the
+                // old and new values never live at once (no copy)
+                const float r = val - ycur;
+                const uint32_t off = col_off + (uint32_t)u * pstep;
+                ycur = yload(u + 2);
+                const double rd = live ? (double)r : 0.0;
+                acc = fma(rd, rd, acc);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, r * a.gscale), gr,
+                                                      live ? off : kDead, 0, NT ? 2 : 0);
+            } else if (live) {
                 float *o = ob + (int64_t)u * plane_out;
                 if (NT) {
                     if (a.mask & 1u) __builtin_nontemporal_store(val, o + choff[0]);
@@ -239,11 +297,34 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
                     if (a.mask & 8u) o[choff[3]] = gz;
                 }
             }
+        };
+        int u = 0;
+        for (; u + 1 < a.rx; u += 2) {
+            step(u, y0);
+            step(u + 1, y1);
+        }
+        if (u < a.rx) step(u, y0);
+      };
+        if (single) walk(std::true_type{});
+        else walk(std::false_type{});
+    }
+
+    if (RESID) {
+        // fixed-order sum of the item: lanes by a shuffle tree (lane 0's
+        // result), then waves in order
+        __shared__ double wsum[8];
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) wsum[wave] = acc;
+        lds_barrier();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int q = 0; q < nwaves; ++q) t += wsum[q];
+            a.partials[item] = t;
         }
     }
 }
 
-template <int WAVES, bool NT>
+template <int WAVES, bool NT, bool RESID>
 __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) {
     extern __shared__ float4 dyn_lds[];
     SepSmem sm = carve(dyn_lds, a.rx, a.slab);
@@ -274,10 +355,12 @@ __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) 
             nrows = min(a.rows, a.ry - row0);
             col0 = (r % a.ncolt) * kWave;
         }
+        // the item's index in the default order, whatever order runs it
+        const int64_t item = (int64_t)b * per + (row0 / a.rows) * a.ncolt + col0 / kWave;
         const int p = a.blocks[b].degree[0];
-        if (p == 3) sep_item<3, NT>(a, b, row0, nrows, col0, sm);
-        else if (p == 2) sep_item<2, NT>(a, b, row0, nrows, col0, sm);
-        else sep_item<1, NT>(a, b, row0, nrows, col0, sm);
+        if (p == 3) sep_item<3, NT, RESID>(a, b, row0, nrows, col0, item, sm);
+        else if (p == 2) sep_item<2, NT, RESID>(a, b, row0, nrows, col0, item, sm);
+        else sep_item<1, NT, RESID>(a, b, row0, nrows, col0, item, sm);
     }
 }
 
@@ -345,19 +428,29 @@ __global__ __launch_bounds__(256) void decode_plain_kernel(const fa_block *block
     }
 }
 
+// sumsq[b] = sum of block b's per-item partials, in item order
+__global__ void residual_combine_kernel(const double *partials, int nblocks, int per,
+                                        double *sumsq) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    double t = 0.0;
+    for (int k = 0; k < per; ++k) t += partials[(int64_t)b * per + k];
+    sumsq[b] = t;
+}
+
 }  // namespace
 
-template <bool NT>
+template <bool NT, bool RESID>
 hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
     const size_t lds = sep_lds_bytes(a.rx, a.slab);
     // raise the dynamic LDS limit once per process to the largest layout
     static const hipError_t attr = [] {
         const int most = (int)sep_lds_bytes(kMaxRes, kSlabMax);
         hipError_t r = hipSuccess, e;
-        const void *ks[4] = {reinterpret_cast<const void *>(&decode_sep_kernel<1, NT>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<2, NT>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<4, NT>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<8, NT>)};
+        const void *ks[4] = {reinterpret_cast<const void *>(&decode_sep_kernel<1, NT, RESID>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<2, NT, RESID>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<4, NT, RESID>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<8, NT, RESID>)};
         for (const void *k : ks)
             if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, most)) !=
                 hipSuccess)
@@ -366,16 +459,27 @@ hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s)
     }();
     if (attr != hipSuccess) return attr;
     switch (waves) {
-    case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT>), dim3(grid), dim3(128), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT>), dim3(grid), dim3(256), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((decode_sep_kernel<8, NT>), dim3(grid), dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((decode_sep_kernel<1, NT>), dim3(grid), dim3(64), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT, RESID>), dim3(grid), dim3(128), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT, RESID>), dim3(grid), dim3(256), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((decode_sep_kernel<8, NT, RESID>), dim3(grid), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((decode_sep_kernel<1, NT, RESID>), dim3(grid), dim3(64), lds, s, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
-    return a.nt_store ? launch_sep<true>(a, waves, grid, s) : launch_sep<false>(a, waves, grid, s);
+    if (a.samples)
+        return a.nt_store ? launch_sep<true, true>(a, waves, grid, s)
+                          : launch_sep<false, true>(a, waves, grid, s);
+    return a.nt_store ? launch_sep<true, false>(a, waves, grid, s)
+                      : launch_sep<false, false>(a, waves, grid, s);
+}
+
+hipError_t launch_residual_combine(const double *partials, int nblocks, int per, double *sumsq,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(residual_combine_kernel, dim3((nblocks + 255) / 256), dim3(256), 0, s,
+                       partials, nblocks, per, sumsq);
+    return hipGetLastError();
 }
 
 hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,

@@ -53,6 +53,10 @@ __device__ __forceinline__ int span_from_guess(int n, int p, KP t, float u, int 
 template <int P, typename KP>
 __device__ __forceinline__ void basis_ders(KP t, int s, float u, float (&N)[P + 1],
                                            float (&D)[P + 1]) {
+    // no fused operations: the values do not depend on how the compiler
+    // contracts the code it is inlined into (kernels that must agree bit
+    // for bit, such as the decode and its residual form, share them)
+#pragma clang fp contract(off)
     float left[P + 1], right[P + 1], low[P + 1];
     N[0] = 1.0f;
 #pragma unroll
@@ -133,6 +137,7 @@ __device__ __forceinline__ void basis_ders_win(const float (&tw)[2 * P], float u
 // zero padded anyway, as in the dense matrix-core contraction).
 __device__ __forceinline__ void basis_ders_rt(const float *t, int s, float u, int p,
                                               float (&N)[4], float (&D)[4]) {
+#pragma clang fp contract(off)
     float left[4] = {0, 0, 0, 0}, right[4] = {0, 0, 0, 0}, low[4] = {0, 0, 0, 0};
     N[0] = 1.0f;
     N[1] = N[2] = N[3] = 0.0f;

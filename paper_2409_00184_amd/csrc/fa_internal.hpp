@@ -31,10 +31,18 @@ struct DecodeLaunch {
     int slab;                // LDS slab floats
     int nt_store;            // 1: non-temporal stores
     float *out;
+    // residual form (value channel only, FP32): out = gscale * (f - samples),
+    // per-item FP64 sums of (f - samples)^2 into partials[item]
+    const float *samples;    // null: plain decode
+    float gscale;
+    double *partials;
 };
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s);
 hipError_t launch_decode_mfma(const DecodeLaunch &a, int waves, int grid, hipStream_t s);
+// per-block sums of the per-item partials of the residual decode
+hipError_t launch_residual_combine(const double *partials, int nblocks, int per, double *sumsq,
+                                   hipStream_t s);
 hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,
                                const float *ctrl, int rx, int ry, int rz, uint32_t mask,
                                float *out, hipStream_t s);

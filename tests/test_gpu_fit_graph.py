@@ -30,15 +30,20 @@ def _fit_case(fa, b, y, P0, res):
 
 
 def _oracle_grad(b, P0, y, res):
-    """FP64: r = B P - y, grad = (2/M) B^T r, and (2/M) B^T |r| (its
-    rounding scale: the value basis is non-negative)."""
+    """FP64: r = B P - y, grad = (2/M) B^T r, and the two rounding scales of
+    an FP32 gradient: (2/M) B^T |r| (the adjoint's own sums) and
+    (2/M) B^T (B |P|) (the decoded values' rounding, up to 64 u32 B|P| per
+    voxel, carried through the residual); the value basis is non-negative,
+    so B^T and B of non-negative vectors are their absolute sums."""
     ob = oracle_blocks(b, P0.astype(np.float64))
     f = oracle.decode_blocks(ob, res, 1)
     r = f - y.reshape(f.shape).astype(np.float64)
     M = r.size
     g = oracle.decode_adjoint(ob, res, r, 1) * (2.0 / M)
     ga = oracle.decode_adjoint(ob, res, np.abs(r), 1) * (2.0 / M)
-    return g, ga, float((r ** 2).mean()), f
+    S = oracle.decode_blocks(oracle_blocks(b, np.abs(P0.astype(np.float64))), res, 1)
+    gs = oracle.decode_adjoint(ob, res, S, 1) * (2.0 / M)
+    return g, ga, float((r ** 2).mean()), f, gs
 
 
 @pytest.mark.parametrize("nblocks,resn", [(6, 24), (256, 64)])
@@ -53,14 +58,14 @@ def test_fit_gradient_vs_oracle_and_fd(fa, nblocks, resn):
     g = fi.rng(61)
     P0 = (0.5 * g.normal(size=b.ctrl.size)).astype(np.float32)
     m, grad, loss = _fit_case(fa, b, y, P0, res)
-    go, ga, lo, f = _oracle_grad(b, P0, y, res)
+    go, ga, lo, f, gs = _oracle_grad(b, P0, y, res)
     assert abs(loss - lo) <= 1e-5 * lo
     valid = np.zeros(b.ctrl.size, bool)
     for k in range(b.nblocks):
         o = int(b.ctrl_off[k])
         valid[o:o + int(np.prod(b.ncp[k]))] = True
     err = np.abs(grad - go)[valid]
-    lim = 256 * U32 * ga[valid] + 1e-30
+    lim = 256 * U32 * ga[valid] + 64 * U32 * gs[valid] + 1e-30
     assert np.all(err <= lim), float((err / lim).max())
     # central differences of the FP64 loss on 64 seeded control points
     h = 1e-3
@@ -99,18 +104,56 @@ def test_fused_mse_gradient_vs_oracle(fa, nblocks, resn):
     loss = fa.FAFitMSE.apply(ctrl, m, res, yt, plan)
     loss.backward()
     grad = ctrl.grad.detach().cpu().numpy().astype(np.float64)
-    go, ga, lo, _ = _oracle_grad(b, P0, y, res)
+    go, ga, lo, _, gs = _oracle_grad(b, P0, y, res)
     assert abs(float(loss) - lo) <= 1e-5 * lo
     valid = np.zeros(b.ctrl.size, bool)
     for k in range(b.nblocks):
         o = int(b.ctrl_off[k])
         valid[o:o + int(np.prod(b.ncp[k]))] = True
     err = np.abs(grad - go)[valid]
-    lim = 256 * U32 * ga[valid] + 1e-30
+    lim = 256 * U32 * ga[valid] + 64 * U32 * gs[valid] + 1e-30
     assert np.all(err <= lim), float((err / lim).max())
     _, g2, l2 = _fit_case(fa, b, y, P0, res)
     assert abs(float(loss) - l2) <= 1e-5 * l2
     assert np.abs(grad - g2)[valid].max() <= 1e-5 * np.abs(g2[valid]).max()
+
+
+@pytest.mark.parametrize("res,tune", [
+    ((64, 64, 64), None),                       # default schedule
+    ((23, 17, 41), (4, 4, 768, 0, 4096, 1)),    # ragged grid, ordinary stores
+    ((40, 48, 70), (16, 8, 1 << 20, 0, 4096, 0)),  # z tiles, slab restaged in x chunks
+])
+def test_decode_residual_matches_decode_then_mse(fa, res, tune):
+    """The fused value decode + residual equals fa_decode_blocks followed by
+    fa_mse_grad bit for bit in the cotangent, and in sumsq up to the order
+    of the FP64 sums (checked against an FP64 sum of the same residuals)."""
+    say("decode residual", res, tune)
+    b = mixed_batch(66, 9, ncp_lo=4, ncp_hi=32)
+    m = models(b)
+    g = fi.rng(67)
+    y = torch.as_tensor(g.normal(size=(b.nblocks,) + res).astype(np.float32)).cuda()
+    nvox = int(np.prod(res))
+    scale = 2.0 / (b.nblocks * nvox)
+    plan = fa.Plan(m, res, *tune) if tune else fa.Plan(m, res)
+    grad, sumsq = fa.decode_residual(m, res, y, scale, plan=plan)
+    f = fa.decode(m, res, 1, plan=plan)
+    ref_g = torch.empty_like(y)
+    ref_s = torch.empty(b.nblocks, dtype=torch.float64, device="cuda")
+    st = fa.lib.fa_mse_grad(fa._ptr(f), fa._ptr(y), b.nblocks, nvox, scale, fa._ptr(ref_g),
+                            fa._ptr(ref_s), fa._stream(None))
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(grad, ref_g)
+    # the residual as both kernels form it (one FP32 subtraction), squared
+    # and summed in FP64
+    r64 = (f.reshape(b.nblocks, -1) - y.reshape(b.nblocks, -1)).double()
+    exact = (r64 * r64).sum(1)
+    assert torch.allclose(sumsq, exact, rtol=1e-12, atol=0), (sumsq - exact).abs().max()
+    assert torch.allclose(ref_s, exact, rtol=1e-12, atol=0)
+    # the default order (no plan) gives the same values
+    g2, s2 = fa.decode_residual(m, res, y, scale,
+                                tune=fa.FATune(*tune) if tune else None)
+    assert torch.equal(g2, grad) and torch.equal(s2, sumsq)
 
 
 def test_fit_converges(fa):
