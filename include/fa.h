@@ -397,6 +397,9 @@ int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t d
  * degree `degree` on every axis) and its error map entry is written:
  *   errs[(b * ncand + (n - ncp_lo)) * 2 + {0, 1}] = (max, rms) as
  *   fa_model_errors, ncand = ncp_hi - ncp_lo + 1.
+ * Each candidate's value decode is reduced to its error-map entry as it is
+ * computed (never stored): max |f - y| exact, the sum of squares in FP64 in
+ * a fixed order, so the map is deterministic.
  *   samples    device FP32 [nblocks][res0][res1][res2]
  *   workspace  device, >= fa_ncp_search_workspace(...) bytes, 256-B aligned
  * Requires degree + 1 <= ncp_lo <= ncp_hi <= min(res) (FA_ERR_INVALID_ARG

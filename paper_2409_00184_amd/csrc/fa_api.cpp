@@ -72,6 +72,37 @@ bool tune_ok(const Tune &t) {
            (t.kernel == 0 || t.kernel == 1);
 }
 
+// launch arguments of a grid decode (default item order unless work is set)
+DecodeLaunch grid_args(const fa_block *blocks, int32_t nblocks, const float *knots,
+                       const void *ctrl, fa_dtype dtype, const int32_t res[3], uint32_t mask,
+                       const Tune &t, const fa_work *work, const int32_t *wg_off, float *out) {
+    DecodeLaunch a{};
+    a.blocks = blocks;
+    a.knots = knots;
+    a.ctrl = ctrl;
+    a.dtype = dtype;
+    a.rx = res[0];
+    a.ry = res[1];
+    a.rz = res[2];
+    a.mask = mask;
+    a.nch = popcount4(mask);
+    a.work = work;
+    a.wg_off = wg_off;
+    a.rows = t.rows;
+    a.nrowt = (res[1] + t.rows - 1) / t.rows;
+    a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
+    a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
+    a.slab = t.slab;
+    a.nt_store = t.store == 0;
+    a.out = out;
+    return a;
+}
+
+// work items per block of a grid decode in the default order
+int64_t items_per_block(const int32_t res[3], const Tune &t) {
+    return (int64_t)((res[1] + t.rows - 1) / t.rows) * ((res[2] + kWaveLanes - 1) / kWaveLanes);
+}
+
 
 }  // namespace
 
@@ -219,25 +250,8 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
-    DecodeLaunch a{};
-    a.blocks = blocks;
-    a.knots = knots;
-    a.ctrl = ctrl;
-    a.dtype = dtype;
-    a.rx = res[0];
-    a.ry = res[1];
-    a.rz = res[2];
-    a.mask = mask;
-    a.nch = popcount4(mask);
-    a.work = work;
-    a.wg_off = wg_off;
-    a.rows = t.rows;
-    a.nrowt = (res[1] + t.rows - 1) / t.rows;
-    a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
-    a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
-    a.slab = t.slab;
-    a.nt_store = t.store == 0;
-    a.out = out;
+    const DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, dtype, res, mask, t, work,
+                                     wg_off, out);
     int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
     hipError_t e;
     if (t.kernel == 1) e = launch_decode_mfma(a, t.waves, grid, (hipStream_t)stream);
@@ -250,8 +264,7 @@ int64_t fa_decode_residual_workspace(int32_t nblocks, const int32_t res[3], cons
     if (nblocks <= 0 || !res_ok(res) || !res_supported(res)) return -1;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return -1;
-    const int64_t per = (int64_t)((res[1] + t.rows - 1) / t.rows) * ((res[2] + kWaveLanes - 1) / kWaveLanes);
-    return (int64_t)nblocks * per * (int64_t)sizeof(double);
+    return (int64_t)nblocks * items_per_block(res, t) * (int64_t)sizeof(double);
 }
 
 fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const float *knots,
@@ -271,25 +284,8 @@ fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const floa
     if (t.kernel != 0) return FA_ERR_UNSUPPORTED;
     const int64_t need = fa_decode_residual_workspace(nblocks, res, tune);
     if (need < 0 || workspace_bytes < need) return FA_ERR_INVALID_ARG;
-    DecodeLaunch a{};
-    a.blocks = blocks;
-    a.knots = knots;
-    a.ctrl = ctrl;
-    a.dtype = FA_F32;
-    a.rx = res[0];
-    a.ry = res[1];
-    a.rz = res[2];
-    a.mask = 1u;
-    a.nch = 1;
-    a.work = work;
-    a.wg_off = wg_off;
-    a.rows = t.rows;
-    a.nrowt = (res[1] + t.rows - 1) / t.rows;
-    a.ncolt = (res[2] + kWaveLanes - 1) / kWaveLanes;
-    a.nitems = (int64_t)nblocks * a.nrowt * a.ncolt;
-    a.slab = t.slab;
-    a.nt_store = t.store == 0;
-    a.out = grad;
+    DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, FA_F32, res, 1u, t, work, wg_off,
+                               grad);
     a.samples = samples;
     a.gscale = grad_scale;
     a.partials = static_cast<double *>(workspace);
@@ -509,28 +505,21 @@ namespace {
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct SearchLayout {
-    int64_t desc, knots, ctrl, decoded, fitws, part, total, cstride;
+    int64_t desc, knots, ctrl, fitws, part, total, cstride;
 };
-
-// residual partial sums of the search: enough chunks per block to give the
-// reduction about 1024 workgroups
-int search_chunks(int32_t nblocks) {
-    const int c = (1024 + nblocks - 1) / nblocks;
-    return c < 1 ? 1 : (c > 64 ? 64 : c);
-}
 
 SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree,
                            int32_t ncp_hi) {
     SearchLayout L{};
-    const int64_t vox = (int64_t)res[0] * res[1] * res[2];
     L.cstride = align_up((int64_t)ncp_hi * ncp_hi * ncp_hi, 64);
     L.desc = 0;
     L.knots = align_up(L.desc + (int64_t)nblocks * (int64_t)sizeof(fa_block), 256);
     L.ctrl = align_up(L.knots + 3 * (int64_t)(ncp_hi + degree + 1) * 4, 256);
-    L.decoded = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
-    L.fitws = align_up(L.decoded + (int64_t)nblocks * vox * 4, 256);
+    L.fitws = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
     L.part = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
-    L.total = align_up(L.part + (int64_t)nblocks * search_chunks(nblocks) * 16, 256);
+    // (max, sum of squares) per decode item
+    L.total = align_up(L.part + (int64_t)nblocks * items_per_block(res, resolve(nullptr)) * 16,
+                       256);
     return L;
 }
 
@@ -569,21 +558,29 @@ fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res
     fa_block *desc = reinterpret_cast<fa_block *>(w + L.desc);
     float *knots = reinterpret_cast<float *>(w + L.knots);
     float *ctrl = reinterpret_cast<float *>(w + L.ctrl);
-    float *decoded = reinterpret_cast<float *>(w + L.decoded);
     const int ncand = ncp_hi - ncp_lo + 1;
+    const Tune t = resolve(nullptr);
+    const int64_t vox = (int64_t)res[0] * res[1] * res[2];
     // from the largest NCP down, as the in-level search runs (Sec. 4.2.1)
     for (int n = ncp_hi; n >= ncp_lo; --n) {
         hipError_t e = launch_candidate(desc, knots, nblocks, n, degree, L.cstride, s);
         if (e != hipSuccess) return FA_ERR_DEVICE;
-        fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, n, w + L.fitws,
-                                     L.total - L.fitws, stream);
+        const fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, n,
+                                           w + L.fitws, L.part - L.fitws, stream);
         if (st != FA_OK) return st;
-        st = fa_decode_blocks(desc, nblocks, knots, ctrl, FA_F32, res, 1u, nullptr, nullptr,
-                              nullptr, 0, decoded, stream);
-        if (st != FA_OK) return st;
-        e = launch_residual(samples, decoded, (int64_t)res[0] * res[1] * res[2], nblocks,
-                            errs + 2 * (n - ncp_lo), 2 * (int64_t)ncand, s,
-                            search_chunks(nblocks), reinterpret_cast<double *>(w + L.part));
+        // the candidate's value decode reduced straight to its error-map
+        // entry (the decode itself is never stored)
+        DecodeLaunch a = grid_args(desc, nblocks, knots, ctrl, FA_F32, res, 1u, t, nullptr,
+                                   nullptr, nullptr);
+        a.samples = samples;
+        a.partials = reinterpret_cast<double *>(w + L.part);
+        a.errs = errs + 2 * (n - ncp_lo);
+        a.errs_stride = 2 * (int64_t)ncand;
+        e = launch_decode_sep(a, t.waves, (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems)),
+                              s);
+        if (e == hipSuccess)
+            e = launch_errors_combine(a.partials, nblocks, a.nrowt * a.ncolt, vox, a.errs,
+                                      a.errs_stride, s);
         if (e != hipSuccess) return FA_ERR_DEVICE;
     }
     return FA_OK;

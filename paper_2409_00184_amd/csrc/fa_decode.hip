@@ -18,7 +18,7 @@
 //   workgroup runs the items a host plan assigned to it, or a grid-stride
 //   share of the default order.
 //
-// The residual form (RESID) decodes the value channel only and, instead of
+// The residual form (MODE 1) decodes the value channel only and, instead of
 //   the value f, stores gscale * (f - samples) for a fit's loss, summing
 //   (f - samples)^2 in FP64 per lane (x order), per wave (fixed shuffle
 //   tree) and per work item (waves in order) into one partial per item; a
@@ -26,6 +26,11 @@
 //   are read one x position ahead through a buffer resource, and dead lanes
 //   load and store at an offset outside every resource (no branch), so the
 //   x walk issues a fixed number of memory operations per step.
+// The error form (MODE 2) reads the samples the same way and stores nothing per
+//   voxel: each item leaves max |f - samples| and the FP64 sum of squares,
+//   and a second kernel turns them into each block's (max, rms) error, the
+//   error-map entry of the adaptive NCP search, without the decode ever
+//   reaching memory.
 //
 // decode_plain: the baseline -- one thread per voxel, one launch per block,
 //   each thread doing its own span searches, basis evaluation and (p+1)^3
@@ -83,7 +88,8 @@ __device__ __forceinline__ float comp(const float4 &v, int r) {
     return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
 }
 
-template <int P, bool NT, bool RESID>
+// MODE 0: decode, 1: residual form, 2: error form
+template <int P, bool NT, int MODE>
 __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0, int64_t item,
                          SepSmem &sm) {
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -93,6 +99,8 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     const int64_t koff = B.knot_off, coff = B.ctrl_off;
     const float scale = B.scale;
     const int nkn = nx + ny + nz + 3 * (P + 1);
+    constexpr bool RESID = MODE != 0;  // reads the samples
+    constexpr bool GRAD = MODE == 1;   // stores the scaled residual
 
     lds_barrier();  // the previous item is done with the shared buffers
     for (int e = tid; e < nkn; e += nthr) sm.kn[e] = a.knots[koff + e];
@@ -163,10 +171,11 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     // resources (value channel only, so both have the layout [u][v][w])
     constexpr uint32_t kDead = 0xfffffff0u;  // beyond every resource
     double acc = 0.0;
+    float amax = 0.0f;
     const __amdgpu_buffer_rsrc_t yr =
         make_rsrc(RESID ? a.samples + (int64_t)b * vox : a.out, RESID ? (uint32_t)vox * 4u : 0u);
     const __amdgpu_buffer_rsrc_t gr =
-        make_rsrc(a.out + (int64_t)b * vox, RESID ? (uint32_t)vox * 4u : 0u);
+        make_rsrc(GRAD ? a.out + (int64_t)b * vox : a.samples, GRAD ? (uint32_t)vox * 4u : 0u);
 
     for (int rb = 0; rb < nrows; rb += nwaves) {
         const int rr = rb + wave;
@@ -213,7 +222,7 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         // counter wait at a step is the same on entry as in the loop (the
         // stores go beyond the resource and are dropped)
         auto ydummy = [&]() {
-            if (RESID) __builtin_amdgcn_raw_buffer_store_b32(0u, gr, kDead, 0, 0);
+            if (GRAD) __builtin_amdgcn_raw_buffer_store_b32(0u, gr, kDead, 0, 0);
         };
         float y0 = yload(0);
         ydummy();
@@ -281,8 +290,11 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
                 ycur = yload(u + 2);
                 const double rd = live ? (double)r : 0.0;
                 acc = fma(rd, rd, acc);
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, r * a.gscale), gr,
-                                                      live ? off : kDead, 0, NT ? 2 : 0);
+                if (GRAD)
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, r * a.gscale),
+                                                          gr, live ? off : kDead, 0, NT ? 2 : 0);
+                else
+                    amax = fmaxf(amax, live ? fabsf(r) : 0.0f);
             } else if (live) {
                 float *o = ob + (int64_t)u * plane_out;
                 if (NT) {
@@ -313,18 +325,34 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         // fixed-order sum of the item: lanes by a shuffle tree (lane 0's
         // result), then waves in order
         __shared__ double wsum[8];
-        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) wsum[wave] = acc;
+        __shared__ float wmax[8];
+        for (int off = 32; off >= 1; off >>= 1) {
+            acc += __shfl_xor(acc, off);
+            if (!GRAD) amax = fmaxf(amax, __shfl_xor(amax, off));
+        }
+        if (lane == 0) {
+            wsum[wave] = acc;
+            wmax[wave] = amax;
+        }
         lds_barrier();
         if (tid == 0) {
             double t = 0.0;
-            for (int q = 0; q < nwaves; ++q) t += wsum[q];
-            a.partials[item] = t;
+            float m = 0.0f;
+            for (int q = 0; q < nwaves; ++q) {
+                t += wsum[q];
+                m = fmaxf(m, wmax[q]);
+            }
+            if (GRAD) {
+                a.partials[item] = t;
+            } else {
+                a.partials[2 * item] = (double)m;
+                a.partials[2 * item + 1] = t;
+            }
         }
     }
 }
 
-template <int WAVES, bool NT, bool RESID>
+template <int WAVES, bool NT, int MODE>
 __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) {
     extern __shared__ float4 dyn_lds[];
     SepSmem sm = carve(dyn_lds, a.rx, a.slab);
@@ -358,9 +386,9 @@ __global__ __launch_bounds__(WAVES * 64) void decode_sep_kernel(DecodeLaunch a) 
         // the item's index in the default order, whatever order runs it
         const int64_t item = (int64_t)b * per + (row0 / a.rows) * a.ncolt + col0 / kWave;
         const int p = a.blocks[b].degree[0];
-        if (p == 3) sep_item<3, NT, RESID>(a, b, row0, nrows, col0, item, sm);
-        else if (p == 2) sep_item<2, NT, RESID>(a, b, row0, nrows, col0, item, sm);
-        else sep_item<1, NT, RESID>(a, b, row0, nrows, col0, item, sm);
+        if (p == 3) sep_item<3, NT, MODE>(a, b, row0, nrows, col0, item, sm);
+        else if (p == 2) sep_item<2, NT, MODE>(a, b, row0, nrows, col0, item, sm);
+        else sep_item<1, NT, MODE>(a, b, row0, nrows, col0, item, sm);
     }
 }
 
@@ -438,19 +466,34 @@ __global__ void residual_combine_kernel(const double *partials, int nblocks, int
     sumsq[b] = t;
 }
 
+// errs[b * stride + {0, 1}] = (max, sqrt(sum / vox)) of block b's per-item
+// (max, sum of squares) partials, in item order
+__global__ void errors_combine_kernel(const double *partials, int nblocks, int per, int64_t vox,
+                                      float *errs, int64_t stride) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    double m = 0.0, t = 0.0;
+    for (int k = 0; k < per; ++k) {
+        m = fmax(m, partials[2 * ((int64_t)b * per + k)]);
+        t += partials[2 * ((int64_t)b * per + k) + 1];
+    }
+    errs[(int64_t)b * stride] = (float)m;
+    errs[(int64_t)b * stride + 1] = (float)sqrt(t / (double)vox);
+}
+
 }  // namespace
 
-template <bool NT, bool RESID>
+template <bool NT, int MODE>
 hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
     const size_t lds = sep_lds_bytes(a.rx, a.slab);
     // raise the dynamic LDS limit once per process to the largest layout
     static const hipError_t attr = [] {
         const int most = (int)sep_lds_bytes(kMaxRes, kSlabMax);
         hipError_t r = hipSuccess, e;
-        const void *ks[4] = {reinterpret_cast<const void *>(&decode_sep_kernel<1, NT, RESID>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<2, NT, RESID>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<4, NT, RESID>),
-                             reinterpret_cast<const void *>(&decode_sep_kernel<8, NT, RESID>)};
+        const void *ks[4] = {reinterpret_cast<const void *>(&decode_sep_kernel<1, NT, MODE>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<2, NT, MODE>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<4, NT, MODE>),
+                             reinterpret_cast<const void *>(&decode_sep_kernel<8, NT, MODE>)};
         for (const void *k : ks)
             if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, most)) !=
                 hipSuccess)
@@ -459,26 +502,34 @@ hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s)
     }();
     if (attr != hipSuccess) return attr;
     switch (waves) {
-    case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT, RESID>), dim3(grid), dim3(128), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT, RESID>), dim3(grid), dim3(256), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((decode_sep_kernel<8, NT, RESID>), dim3(grid), dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((decode_sep_kernel<1, NT, RESID>), dim3(grid), dim3(64), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((decode_sep_kernel<2, NT, MODE>), dim3(grid), dim3(128), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((decode_sep_kernel<4, NT, MODE>), dim3(grid), dim3(256), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((decode_sep_kernel<8, NT, MODE>), dim3(grid), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((decode_sep_kernel<1, NT, MODE>), dim3(grid), dim3(64), lds, s, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
+    if (a.samples && a.errs) return launch_sep<false, 2>(a, waves, grid, s);
     if (a.samples)
-        return a.nt_store ? launch_sep<true, true>(a, waves, grid, s)
-                          : launch_sep<false, true>(a, waves, grid, s);
-    return a.nt_store ? launch_sep<true, false>(a, waves, grid, s)
-                      : launch_sep<false, false>(a, waves, grid, s);
+        return a.nt_store ? launch_sep<true, 1>(a, waves, grid, s)
+                          : launch_sep<false, 1>(a, waves, grid, s);
+    return a.nt_store ? launch_sep<true, 0>(a, waves, grid, s)
+                      : launch_sep<false, 0>(a, waves, grid, s);
 }
 
 hipError_t launch_residual_combine(const double *partials, int nblocks, int per, double *sumsq,
                                    hipStream_t s) {
     hipLaunchKernelGGL(residual_combine_kernel, dim3((nblocks + 255) / 256), dim3(256), 0, s,
                        partials, nblocks, per, sumsq);
+    return hipGetLastError();
+}
+
+hipError_t launch_errors_combine(const double *partials, int nblocks, int per, int64_t vox,
+                                 float *errs, int64_t stride, hipStream_t s) {
+    hipLaunchKernelGGL(errors_combine_kernel, dim3((nblocks + 255) / 256), dim3(256), 0, s,
+                       partials, nblocks, per, vox, errs, stride);
     return hipGetLastError();
 }
 

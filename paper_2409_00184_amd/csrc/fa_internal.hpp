@@ -36,6 +36,10 @@ struct DecodeLaunch {
     const float *samples;    // null: plain decode
     float gscale;
     double *partials;
+    // error form (samples set, errs set, nothing stored per voxel): per-item
+    // max |f - samples| and FP64 sum of squares into partials[2 item + {0,1}]
+    float *errs;
+    int64_t errs_stride;
 };
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s);
@@ -43,6 +47,10 @@ hipError_t launch_decode_mfma(const DecodeLaunch &a, int waves, int grid, hipStr
 // per-block sums of the per-item partials of the residual decode
 hipError_t launch_residual_combine(const double *partials, int nblocks, int per, double *sumsq,
                                    hipStream_t s);
+// errs[b * stride + {0, 1}] = (max, rms) of block b from the error form's
+// per-item partials, items in order
+hipError_t launch_errors_combine(const double *partials, int nblocks, int per, int64_t vox,
+                                 float *errs, int64_t stride, hipStream_t s);
 hipError_t launch_decode_plain(const fa_block *blocks, int nblocks, const float *knots,
                                const float *ctrl, int rx, int ry, int rz, uint32_t mask,
                                float *out, hipStream_t s);
