@@ -491,23 +491,25 @@ def bench_f2(args):
     graph, _ = fa.capture(run)
     ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
     del graph
-    # per-stage breakdown at a few NCPs (fit = adjoint + Gram solve; errors =
-    # value decode + residual reduction), HIP events on the launch stream
+    # per-stage breakdown at a few NCPs: the fit alone (adjoint + Gram
+    # solve) and the search over that one candidate (descriptors, fit, value
+    # decode reduced to the error-map entry), HIP events on the launch stream
     stages = {}
     for n in (8, 32, 64):
         m = fa.uniform_models(np.full((nb, 3), n), np.full(nb, p))
-        dec = torch.empty_like(Y)
         fws = torch.empty(fa.lib.fa_fit_workspace(nb, fa._i32x3((R, R, R)), n),
                           dtype=torch.uint8, device="cuda")
         f_ms = timed_steps(lambda: fa.fit(m, (R, R, R), Y, workspace=fws), 5, 2, stream)[1]
-        e_ms = timed_steps(lambda: fa.model_errors(m, (R, R, R), Y, decoded=dec), 5, 2,
-                           stream)[1]
-        stages[str(n)] = {"fit_ms": f_ms, "errors_ms": e_ms}
-        del m, dec, fws
+        one = lambda: fa._check("fa_ncp_search", fa.lib.fa_ncp_search(
+            fa._ptr(Y), nb, fa._i32x3((R, R, R)), p, n, n, fa._ptr(errs), fa._ptr(ws),
+            ws.numel(), fa._stream()))
+        c_ms = timed_steps(one, 5, 2, stream)[1]
+        stages[str(n)] = {"fit_ms": f_ms, "candidate_ms": c_ms, "errors_ms": c_ms - f_ms}
+        del m, fws
     vox = nb * R ** 3
-    # HBM floor of the four passes over the voxels per candidate: the adjoint
-    # reads y, the decode writes f, the residual reads y and f (16 B/voxel)
-    alg = ncand * vox * 16
+    # HBM floor of the two passes over the voxels per candidate: the fit
+    # reads y, the error-map decode reads y (8 B/voxel)
+    alg = ncand * vox * 8
     line = _common(args, "micro-blocks searched/sec (adaptive NCP, Eq. 4)", nb / (ms * 1e-3),
                    "blocks/s", ms, "f32",
                    "F2 in-level adaptive NCP search: 64 micro-blocks of 64^3 FP32 samples "
