@@ -505,18 +505,22 @@ namespace {
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct SearchLayout {
-    int64_t desc, knots, ctrl, fitws, part, total, cstride;
+    int64_t desc, knots, ctrl, fitws, pinv, part, total, cstride, kstride;
 };
 
 SearchLayout search_layout(int32_t nblocks, const int32_t res[3], int32_t degree,
                            int32_t ncp_hi) {
     SearchLayout L{};
+    const int64_t ncand = ncp_hi - (degree + 1) + 1;  // room for every ncp_lo
     L.cstride = align_up((int64_t)ncp_hi * ncp_hi * ncp_hi, 64);
+    L.kstride = 3 * (int64_t)(ncp_hi + degree + 1);
     L.desc = 0;
     L.knots = align_up(L.desc + (int64_t)nblocks * (int64_t)sizeof(fa_block), 256);
-    L.ctrl = align_up(L.knots + 3 * (int64_t)(ncp_hi + degree + 1) * 4, 256);
+    L.ctrl = align_up(L.knots + ncand * L.kstride * 4, 256);
     L.fitws = align_up(L.ctrl + (int64_t)nblocks * L.cstride * 4, 256);
-    L.part = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
+    // per-candidate pseudo-inverses (3 axes each)
+    L.pinv = align_up(L.fitws + fit_workspace_bytes(nblocks, res[0], res[1], ncp_hi), 256);
+    L.part = align_up(L.pinv + ncand * 3 * pinv_doubles() * 8, 256);
     // (max, sum of squares) per decode item
     L.total = align_up(L.part + (int64_t)nblocks * items_per_block(res, resolve(nullptr)) * 16,
                        256);
@@ -561,16 +565,24 @@ fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res
     const int ncand = ncp_hi - ncp_lo + 1;
     const Tune t = resolve(nullptr);
     const int64_t vox = (int64_t)res[0] * res[1] * res[2];
+    double *xall = reinterpret_cast<double *>(w + L.pinv);
+    // every candidate's knots and pseudo-inverses depend on (n, p, res) only:
+    // built once for all candidates, in one launch
+    hipError_t e = launch_pinv_candidates(knots, ncp_lo, ncand, degree, (int)L.kstride, res[0],
+                                          res[1], res[2], xall, s);
+    if (e != hipSuccess) return FA_ERR_DEVICE;
     // from the largest NCP down, as the in-level search runs (Sec. 4.2.1)
     for (int n = ncp_hi; n >= ncp_lo; --n) {
-        hipError_t e = launch_candidate(desc, knots, nblocks, n, degree, L.cstride, s);
+        float *kn = knots + (int64_t)(n - ncp_lo) * L.kstride;
+        e = launch_candidate(desc, kn, nblocks, n, degree, L.cstride, s);
         if (e != hipSuccess) return FA_ERR_DEVICE;
-        const fa_status st = fa_fit_blocks(desc, nblocks, knots, res, samples, ctrl, n,
-                                           w + L.fitws, L.part - L.fitws, stream);
-        if (st != FA_OK) return st;
+        e = launch_fit_shared(desc, nblocks, kn, res[0], res[1], res[2], n, samples,
+                              reinterpret_cast<double *>(w + L.fitws), xall + (int64_t)(n - ncp_lo) * 3 * pinv_doubles(),
+                              ctrl, s);
+        if (e != hipSuccess) return FA_ERR_DEVICE;
         // the candidate's value decode reduced straight to its error-map
         // entry (the decode itself is never stored)
-        DecodeLaunch a = grid_args(desc, nblocks, knots, ctrl, FA_F32, res, 1u, t, nullptr,
+        DecodeLaunch a = grid_args(desc, nblocks, kn, ctrl, FA_F32, res, 1u, t, nullptr,
                                    nullptr, nullptr);
         a.samples = samples;
         a.partials = reinterpret_cast<double *>(w + L.part);

@@ -165,6 +165,38 @@ __global__ __launch_bounds__(kFitThreads) void fit_pinv_kernel(const fa_block *b
     }
 }
 
+// knot j of a clamped uniform vector: t_j = 0 (j <= p), 1 (j >= n), else
+// fl32((j - p) / (n - p))
+__device__ __forceinline__ float candidate_knot(int j, int n, int p) {
+    if (j <= p) return 0.0f;
+    if (j >= n) return 1.0f;
+    return (float)(j - p) / (float)(n - p);
+}
+
+// The search's candidates share one knot vector per NCP (every block, every
+// axis), so their pseudo-inverses are built once per (candidate, axis), all
+// candidates in one launch: knots of candidate c (n = ncp_lo + c) at
+// kall + c * kstride (x, y, z vectors back to back), X_a at
+// xall + (c * 3 + a) * kPinvStride.
+__global__ __launch_bounds__(kFitThreads) void pinv_candidates_kernel(float *kall, int ncp_lo,
+                                                                      int ncand, int p,
+                                                                      int kstride, int r0, int r1,
+                                                                      int r2, double *xall) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    PinvSmem &sm = *reinterpret_cast<PinvSmem *>(smem_raw);
+    for (int item = blockIdx.x; item < ncand * 3; item += gridDim.x) {
+        const int c = item / 3, a = item - 3 * c, n = ncp_lo + c, nk = n + p + 1;
+        float *t = kall + (int64_t)c * kstride + a * nk;
+        for (int j = threadIdx.x; j < nk; j += kFitThreads) t[j] = candidate_knot(j, n, p);
+        __syncthreads();
+        const int Ra = a == 0 ? r0 : (a == 1 ? r1 : r2);
+        build_pinv(sm.w, t, n, p, Ra, &sm.X[0][0], kFitR, 1);
+        double *dst = xall + (int64_t)item * kPinvStride;
+        for (int e = threadIdx.x; e < n * kFitR; e += kFitThreads) dst[e] = (&sm.X[0][0])[e];
+        __syncthreads();
+    }
+}
+
 // FP64 matrix-core contraction tiles: v_mfma_f64_16x16x4f64 takes
 // A[l%16][l/16] and B[l/16][l%16] from lane l and returns D[4r + l/16][l%16]
 // in component r (layout checked on the device).
@@ -186,7 +218,8 @@ struct FitZSmem {
 __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
                                                             const float *knots, int r0, int r1,
                                                             int r2, int max_n, const float *y,
-                                                            const double *Xg, double *T) {
+                                                            const double *Xg, int64_t xstride,
+                                                            double *T) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitZSmem &sm = *reinterpret_cast<FitZSmem *>(smem_raw);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -199,7 +232,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
         const fa_block b = blocks[bi];
         const int nz = b.ncp[2];
         if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
-        const double *Xz = Xg + ((int64_t)bi * 3 + 2) * kPinvStride;
+        const double *Xz = Xg + (int64_t)bi * xstride + 2 * kPinvStride;
         for (int e = tid; e < nz * kFitR; e += kFitThreads) {
             const int k = e / kFitR;
             sm.X[k][e - k * kFitR] = Xz[e];
@@ -255,8 +288,8 @@ struct FitXYSmem {
 __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int r0, int r1,
                                                              int max_n, int kgroup,
-                                                             const double *Xg, const double *T,
-                                                             float *ctrl) {
+                                                             const double *Xg, int64_t xstride,
+                                                             const double *T, float *ctrl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitXYSmem &sm = *reinterpret_cast<FitXYSmem *>(smem_raw);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -271,7 +304,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
         const int nx = b.ncp[0], ny = b.ncp[1], nz = b.ncp[2];
         if (k0 >= nz || nz > max_n) continue;
         // the block's X_x and X_y serve every k of the group
-        const double *Xx = Xg + (int64_t)bi * 3 * kPinvStride;
+        const double *Xx = Xg + (int64_t)bi * xstride;
         const double *Xy = Xx + kPinvStride;
         for (int e = tid; e < nx * kFitR; e += kFitThreads) {
             const int i = e / kFitR;
@@ -468,14 +501,7 @@ __global__ void candidate_kernel(fa_block *desc, float *knots, int nblocks, int 
                                  int64_t cstride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nk = n + p + 1;
-    if (i < 3 * nk) {
-        const int j = i % nk;
-        float v;
-        if (j <= p) v = 0.0f;
-        else if (j >= n) v = 1.0f;
-        else v = (float)(j - p) / (float)(n - p);
-        knots[i] = v;
-    }
+    if (i < 3 * nk) knots[i] = candidate_knot(i % nk, n, p);
     if (i < nblocks) {
         fa_block d{};
         d.ncp[0] = d.ncp[1] = d.ncp[2] = n;
@@ -495,37 +521,78 @@ int64_t fit_workspace_bytes(int nblocks, int rx, int ry, int max_n) {
            (int64_t)sizeof(double);
 }
 
-hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,
-                      int rz, int max_n, const float *samples, double *T, float *ctrl,
-                      hipStream_t s) {
+namespace {
+// raise the dynamic LDS limits of the fit kernels once per process
+hipError_t fit_attributes() {
     static const hipError_t attr = [] {
-        hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_z_kernel),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(FitZSmem));
-        hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_xy_kernel),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(FitXYSmem));
-        hipError_t e3 = hipFuncSetAttribute(reinterpret_cast<const void *>(&fit_pinv_kernel),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)sizeof(PinvSmem));
-        return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+        const void *ks[4] = {reinterpret_cast<const void *>(&fit_z_kernel),
+                             reinterpret_cast<const void *>(&fit_xy_kernel),
+                             reinterpret_cast<const void *>(&fit_pinv_kernel),
+                             reinterpret_cast<const void *>(&pinv_candidates_kernel)};
+        const int bytes[4] = {(int)sizeof(FitZSmem), (int)sizeof(FitXYSmem),
+                              (int)sizeof(PinvSmem), (int)sizeof(PinvSmem)};
+        hipError_t r = hipSuccess;
+        for (int i = 0; i < 4; ++i) {
+            const hipError_t e =
+                hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i]);
+            if (e != hipSuccess) r = e;
+        }
+        return r;
     }();
-    if (attr != hipSuccess) return attr;
-    double *Xg = T + (int64_t)nblocks * max_n * rx * ry;
-    const int gp = (int)std::min<int64_t>((int64_t)nblocks * 3, 65536);
-    hipLaunchKernelGGL(fit_pinv_kernel, dim3(gp), dim3(kFitThreads), sizeof(PinvSmem), s, blocks,
-                       nblocks, knots, rx, ry, rz, Xg);
+    return attr;
+}
+
+// the two products of a fit given the pseudo-inverses: block b's X_a at
+// X + b * xstride + a * kPinvStride
+hipError_t launch_fit_products(const fa_block *blocks, int nblocks, const float *knots, int rx,
+                               int ry, int rz, int max_n, const float *samples, double *T,
+                               const double *X, int64_t xstride, float *ctrl, hipStream_t s) {
     const int64_t chunks = ((int64_t)rx * ry + kFitThreads - 1) / kFitThreads;
     const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
     hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
-                       nblocks, knots, rx, ry, rz, max_n, samples, Xg, T);
+                       nblocks, knots, rx, ry, rz, max_n, samples, X, xstride, T);
     // k values per workgroup: as many as keep about 2048 workgroups busy
     const int kgroup = (int)std::max<int64_t>(1, std::min<int64_t>(max_n, (int64_t)nblocks * max_n / 2048));
     const int64_t groups = (max_n + kgroup - 1) / kgroup;
     const int gxy = (int)std::min<int64_t>((int64_t)nblocks * groups, 65536);
     hipLaunchKernelGGL(fit_xy_kernel, dim3(gxy), dim3(kFitThreads), sizeof(FitXYSmem), s, blocks,
-                       nblocks, knots, rx, ry, max_n, kgroup, Xg, T, ctrl);
+                       nblocks, knots, rx, ry, max_n, kgroup, X, xstride, T, ctrl);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fit(const fa_block *blocks, int nblocks, const float *knots, int rx, int ry,
+                      int rz, int max_n, const float *samples, double *T, float *ctrl,
+                      hipStream_t s) {
+    const hipError_t attr = fit_attributes();
+    if (attr != hipSuccess) return attr;
+    double *Xg = T + (int64_t)nblocks * max_n * rx * ry;
+    const int gp = (int)std::min<int64_t>((int64_t)nblocks * 3, 65536);
+    hipLaunchKernelGGL(fit_pinv_kernel, dim3(gp), dim3(kFitThreads), sizeof(PinvSmem), s, blocks,
+                       nblocks, knots, rx, ry, rz, Xg);
+    return launch_fit_products(blocks, nblocks, knots, rx, ry, rz, max_n, samples, T, Xg,
+                               3 * kPinvStride, ctrl, s);
+}
+
+int64_t pinv_doubles() { return kPinvStride; }
+
+hipError_t launch_pinv_candidates(float *kall, int ncp_lo, int ncand, int p, int kstride, int rx,
+                                  int ry, int rz, double *xall, hipStream_t s) {
+    const hipError_t attr = fit_attributes();
+    if (attr != hipSuccess) return attr;
+    const int grid = std::min(ncand * 3, 65536);
+    hipLaunchKernelGGL(pinv_candidates_kernel, dim3(grid), dim3(kFitThreads), sizeof(PinvSmem), s,
+                       kall, ncp_lo, ncand, p, kstride, rx, ry, rz, xall);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_shared(const fa_block *blocks, int nblocks, const float *knots, int rx,
+                             int ry, int rz, int max_n, const float *samples, double *T,
+                             const double *X, float *ctrl, hipStream_t s) {
+    const hipError_t attr = fit_attributes();
+    if (attr != hipSuccess) return attr;
+    return launch_fit_products(blocks, nblocks, knots, rx, ry, rz, max_n, samples, T, X, 0, ctrl,
+                               s);
 }
 
 hipError_t launch_residual(const float *y, const float *f, int64_t vox, int nblocks, float *errs,

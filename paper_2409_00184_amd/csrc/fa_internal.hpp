@@ -100,6 +100,17 @@ hipError_t launch_mse_grad(const float *f, const float *y, int64_t vox, int nblo
                            float *grad, double *sumsq, hipStream_t s);
 hipError_t launch_candidate(fa_block *desc, float *knots, int nblocks, int n, int p,
                             int64_t cstride, hipStream_t s);
+// doubles of one (block or candidate, axis) pseudo-inverse
+int64_t pinv_doubles();
+// knots and per-axis pseudo-inverses of every candidate NCP ncp_lo + c,
+// c < ncand, of a search (clamped uniform knots shared by all blocks):
+// knots at kall + c * kstride, X_a at xall + (3 c + a) * pinv_doubles()
+hipError_t launch_pinv_candidates(float *kall, int ncp_lo, int ncand, int p, int kstride, int rx,
+                                  int ry, int rz, double *xall, hipStream_t s);
+// launch_fit with one set of pseudo-inverses X (3 axes) shared by every block
+hipError_t launch_fit_shared(const fa_block *blocks, int nblocks, const float *knots, int rx,
+                             int ry, int rz, int max_n, const float *samples, double *T,
+                             const double *X, float *ctrl, hipStream_t s);
 
 // One block of a staging gather: its slot in the mapped host cache, where
 // its knots and lattice go in the device batch, and its descriptor.
