@@ -277,14 +277,19 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
 }
 
 struct FitXYSmem {
-    double Xx[kFitN][kXS];  // X_x[i][x]
     double Xy[kFitN][kXS];  // X_y[j][y]
     double S[kFitR][kXS];   // slice T[b][k] as [x][y]
-    double U[kFitN][kXS];   // X_x S
 };
 
 // For each k: P[:, :, k] = X_x T[b][k] X_y^T, two products on the FP64
-// matrix cores (U = X_x S in LDS, then U X_y^T), one workgroup per (b, k).
+// matrix cores, one workgroup per (b, group of k), wave w owning rows
+// 16w..16w+15 of P.  The first product is formed transposed, U^T = S^T X_x^T:
+// its accumulator layout (row 4r + l/16, column l%16 in component r of lane
+// l) is then exactly the A operand of the second product U X_y^T for the K
+// steps 4t + r (t = the U^T tile), so U never leaves registers; the wave's
+// X_x rows are held in registers as the B operand of the first product for
+// every k of the group.  LDS holds X_y and the slice only (two workgroups
+// per CU).
 __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int r0, int r1,
                                                              int max_n, int kgroup,
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
     FitXYSmem &sm = *reinterpret_cast<FitXYSmem *>(smem_raw);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    constexpr int kWaves = kFitThreads / 64;
+    constexpr int kKS = kFitR / 4;  // K steps of a 64-long contraction
     const int64_t lines = (int64_t)r0 * r1;
     const int groups = (max_n + kgroup - 1) / kgroup;
     for (int64_t item = blockIdx.x; item < (int64_t)nblocks * groups; item += gridDim.x) {
@@ -303,17 +308,22 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
         const fa_block b = blocks[bi];
         const int nx = b.ncp[0], ny = b.ncp[1], nz = b.ncp[2];
         if (k0 >= nz || nz > max_n) continue;
-        // the block's X_x and X_y serve every k of the group
         const double *Xx = Xg + (int64_t)bi * xstride;
         const double *Xy = Xx + kPinvStride;
-        for (int e = tid; e < nx * kFitR; e += kFitThreads) {
-            const int i = e / kFitR;
-            sm.Xx[i][e - i * kFitR] = Xx[e];
-        }
         for (int e = tid; e < ny * kFitR; e += kFitThreads) {
             const int j = e / kFitR;
             sm.Xy[j][e - j * kFitR] = Xy[e];
         }
+        // B operand of U^T = S^T X_x^T: X_x[i][x], i = 16 wave + l%16, x = 4 ks + l/16
+        const int i = 16 * wave + lr;
+        const bool rows = 16 * wave < nx;  // the wave has rows of P
+        double xb[kKS];
+#pragma unroll
+        for (int ks = 0; ks < kKS; ++ks) {
+            const int x = 4 * ks + lk;
+            xb[ks] = (i < nx && x < r0) ? Xx[(int64_t)i * kFitR + x] : 0.0;
+        }
+        float *Pb = ctrl + b.ctrl_off;
         const int k1 = min(nz, k0 + kgroup);
         for (int k = k0; k < k1; ++k) {
             const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
@@ -322,55 +332,45 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
                 sm.S[x][e - x * r1] = Tk[e];
             }
             __syncthreads();
-            // U (nx x r1) = X_x (nx x r0) S (r0 x r1): one strip of up to 4
-            // column tiles per row tile, sharing the A operand
-            const int mx = (nx + 15) >> 4, ny1 = (r1 + 15) >> 4, ks0 = (r0 + 3) >> 2;
-            for (int ti = wave; ti < mx; ti += kWaves) {
-                const int i = 16 * ti + lr;
-                f64x4 acc[4];
+            if (rows) {
+                // U^T[yy][i] for the yy tiles t: A = S^T[yy][x] = S[x][yy]
+                f64x4 u[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-                for (int ks = 0; ks < ks0; ++ks) {
+                for (int t = 0; t < 4; ++t) u[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+                // every K step and tile runs (entries outside the slice are
+                // selected to zero: no scalar conditions in the unrolled chains)
+#pragma unroll
+                for (int ks = 0; ks < kKS; ++ks) {
                     const int x = 4 * ks + lk;
-                    const bool xok = x < r0;
-                    const double av = (i < nx && xok) ? sm.Xx[i][x] : 0.0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int yy = 16 * q + lr;
-                        const double bv = (q < ny1 && yy < r1 && xok) ? sm.S[x][yy] : 0.0;
-                        acc[q] = mfma64(av, bv, acc[q]);
+                    for (int t = 0; t < 4; ++t) {
+                        const int yy = 16 * t + lr;
+                        const double sv = sm.S[x][yy];
+                        u[t] = mfma64((yy < r1 && x < r0) ? sv : 0.0, xb[ks], u[t]);
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) sm.U[16 * ti + 4 * r + lk][16 * q + lr] = acc[q][r];
-            }
-            __syncthreads();
-            // P[:, :, k] (nx x ny) = U (nx x r1) X_y^T (r1 x ny), strips as above
-            float *Pb = ctrl + b.ctrl_off;
-            const int my = (ny + 15) >> 4, ks1 = (r1 + 3) >> 2;
-            for (int ti = wave; ti < mx; ti += kWaves) {
-                const int i = 16 * ti + lr;
+                // P[i][j] = sum_yy U[i][yy] X_y[j][yy]: A for K step 4t + r is
+                // component r of u[t] (U[16 wave + l%16][4(4t + r) + l/16])
                 f64x4 acc[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-                for (int ks = 0; ks < ks1; ++ks) {
-                    const int yy = 4 * ks + lk;
-                    const bool yok = yy < r1;
-                    const double av = (i < nx && yok) ? sm.U[i][yy] : 0.0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = 16 * q + lr;
-                        const double bv = (q < my && j < ny && yok) ? sm.Xy[j][yy] : 0.0;
-                        acc[q] = mfma64(av, bv, acc[q]);
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int yy = 4 * (4 * t + r) + lk;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = 16 * q + lr;
+                            const double xv = sm.Xy[j][yy];
+                            acc[q] = mfma64(u[t][r], (j < ny && yy < r1) ? xv : 0.0, acc[q]);
+                        }
                     }
-                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int ii = 16 * ti + 4 * r + lk, jj = 16 * q + lr;
+                        const int ii = 16 * wave + 4 * r + lk, jj = 16 * q + lr;
                         if (ii < nx && jj < ny) Pb[((int64_t)ii * ny + jj) * nz + k] = (float)acc[q][r];
                     }
             }
