@@ -16,10 +16,10 @@
 // badly conditioned).  Three kernels, FP64 throughout:
 //   fit_pinv: X_a of every (block, axis), one workgroup each, into the
 //           caller's workspace,
-//   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (chunks of 256
+//   fit_z:  T[b][k][x][y] = sum_z X_z[k][z] y[b][x][y][z]   (chunks of 128
 //           (x, y) lines staged in LDS, T in the workspace),
 //   fit_xy: for each k, P[:, :, k] = X_x T[b][k] X_y^T        (one workgroup
-//           per (block, k), the slice in LDS),
+//           per (block, group of k), the slice in LDS, X_x T in registers),
 // the dense products of fit_z and fit_xy on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64), and the lattice rounded to FP32 once.
 // residual kernel: one workgroup per block reduces y - f to (max |r|,
@@ -208,13 +208,15 @@ __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
 
 constexpr int kXS = kFitR + 1;  // padded row of an LDS matrix (doubles)
 
+constexpr int kZLines = 128;  // (x, y) lines per fit_z chunk: two workgroups per CU
+
 struct FitZSmem {
     double X[kFitN][kXS];                 // X_z[k][z]
-    float ys[kFitThreads][kFitR + 1];     // staged lines (padded)
+    float ys[kZLines][kFitR + 1];         // staged lines (padded)
 };
 
-// T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y: per chunk of 256
-// lines, a (n_z x R2) x (R2 x 256) product on the FP64 matrix cores.
+// T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y: per chunk of 128
+// lines, a (n_z x R2) x (R2 x 128) product on the FP64 matrix cores.
 __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
                                                             const float *knots, int r0, int r1,
                                                             int r2, int max_n, const float *y,
@@ -225,10 +227,10 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int64_t lines = (int64_t)r0 * r1;
-    const int chunks = (int)((lines + kFitThreads - 1) / kFitThreads);
+    const int chunks = (int)((lines + kZLines - 1) / kZLines);
     for (int64_t item = blockIdx.x; item < (int64_t)nblocks * chunks; item += gridDim.x) {
         const int bi = (int)(item / chunks);
-        const int64_t l0 = (item - (int64_t)bi * chunks) * kFitThreads;
+        const int64_t l0 = (item - (int64_t)bi * chunks) * kZLines;
         const fa_block b = blocks[bi];
         const int nz = b.ncp[2];
         if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *bloc
             const int k = e / kFitR;
             sm.X[k][e - k * kFitR] = Xz[e];
         }
-        const int cl = (int)(lines - l0 < kFitThreads ? lines - l0 : kFitThreads);
+        const int cl = (int)(lines - l0 < kZLines ? lines - l0 : kZLines);
         const float *yb = y + ((int64_t)bi * lines + l0) * r2;
         for (int e = tid; e < cl * r2; e += kFitThreads) {
             const int li = e / r2;
@@ -547,7 +549,7 @@ hipError_t fit_attributes() {
 hipError_t launch_fit_products(const fa_block *blocks, int nblocks, const float *knots, int rx,
                                int ry, int rz, int max_n, const float *samples, double *T,
                                const double *X, int64_t xstride, float *ctrl, hipStream_t s) {
-    const int64_t chunks = ((int64_t)rx * ry + kFitThreads - 1) / kFitThreads;
+    const int64_t chunks = ((int64_t)rx * ry + kZLines - 1) / kZLines;
     const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
     hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
                        nblocks, knots, rx, ry, rz, max_n, samples, X, xstride, T);
