@@ -370,7 +370,8 @@ fa_status fa_mse_grad(const float *decoded, const float *samples, int32_t nblock
  * stored).  grad equals fa_decode_blocks + fa_mse_grad bit for bit; sumsq
  * differs only in the order of its FP64 sum.  Runs the separable VALU
  * kernel (tune->kernel must be 0); tune, work, wg_off, ngroups as in
- * fa_decode_blocks.
+ * fa_decode_blocks, except that waves left at 0 (or a null tune) mean 8
+ * here (one y row per wave at the default 8 rows per item).
  *   samples, grad  device FP32 [nblocks][res0][res1][res2]
  *   sumsq          device FP64 [nblocks]
  *   workspace      device, fa_decode_residual_workspace(...) bytes (one
