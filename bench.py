@@ -156,8 +156,9 @@ def cpu_baseline_fit(batch, y, res, target_s=15.0):
                       f"adjoint, {dt:.1f} s, scaled to the whole batch (optimizer step excluded)"}
 
 
-def err_vs_oracle_decode(batch, out, res, nsample=20000, src=None):
-    """Max |gpu - FP64| / max |FP64| per channel on seeded voxels."""
+def err_vs_oracle_decode(batch, out, res, nsample=20000, src=None, interleaved=False):
+    """Max |gpu - FP64| / max |FP64| per channel on seeded voxels (out planar
+    [nb][4][res] or interleaved [nb][res][4])."""
     import numpy as np
     import torch
 
@@ -170,7 +171,10 @@ def err_vs_oracle_decode(batch, out, res, nsample=20000, src=None):
                        batch.ctrl if src is None else src)
     ref = oracle.decode_samples(ob, res, idx)
     ti = torch.as_tensor(idx, device=out.device).long()
-    got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].double().cpu().numpy()
+    if interleaved:
+        got = out[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].double().cpu().numpy()
+    else:
+        got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].double().cpu().numpy()
     names = ["value", "d/du", "d/dv", "d/dw"]
     return {names[c]: float(np.abs(got[:, c] - ref[:, c]).max() / np.abs(ref[:, c]).max())
             for c in range(4)}
@@ -189,22 +193,34 @@ def bench_c2(args):
     batch = fi.config_c2()
     m = fa.MicroModels.from_batch(batch)
     stream = torch.cuda.current_stream()
-    if args.tune:
-        plan, report = fa.Plan(m, res, *args.tune), [(tuple(args.tune), None)]
-    else:
-        plan, report = autotune.tune(m, res, 15, "f32", use_cache=not args.retune)
+    # the timed form stores one (value, d/du, d/dv, d/dw) record per voxel;
+    # the planar [nb][4][res] form is timed beside it
+    mask = 15 | fa.OUT_INTERLEAVED
+
+    def schedule(mk):
+        if args.tune:
+            return fa.Plan(m, res, *args.tune), [(tuple(args.tune), None)]
+        return autotune.tune(m, res, mk, "f32", use_cache=not args.retune)
+
+    plan, report = schedule(mask)
     log("schedule", [plan.tune.rows_per_item, plan.tune.waves, plan.ngroups,
                      plan.tune.slab_floats, plan.tune.store],
         "fastest candidates", sorted(report, key=lambda r: r[1] or 0)[:6])
-    out = torch.empty((batch.nblocks, 4) + res, dtype=torch.float32, device="cuda")
-    graph, _ = fa.capture(lambda: fa.decode(m, res, 15, plan=plan, out=out))
+    out = torch.empty((batch.nblocks,) + res + (4,), dtype=torch.float32, device="cuda")
+    graph, _ = fa.capture(lambda: fa.decode(m, res, mask, plan=plan, out=out))
     ms, ev_ms, ev_min = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    err = err_vs_oracle_decode(batch, out, res, interleaved=True)
+    del graph, out
+    pplan, _ = schedule(15)
+    out = torch.empty((batch.nblocks, 4) + res, dtype=torch.float32, device="cuda")
+    pgraph, _ = fa.capture(lambda: fa.decode(m, res, 15, plan=pplan, out=out))
+    planar_ms, planar_ev, _ = timed_steps(pgraph.replay, args.steps, args.warmup, stream)
+    del pgraph
     nvox = batch.nblocks * res[0] * res[1] * res[2]
     value = nvox / (ms * 1e-3)
     lattice_bytes = 4 * int(sum(int(n.prod()) for n in batch.ncp))
     alg_bytes = nvox * 16 + lattice_bytes + 4 * batch.knots.size + 64 * batch.nblocks
     achieved = alg_bytes / (ev_ms * 1e-3) / 1e9
-    err = err_vs_oracle_decode(batch, out, res)
     line = {
         "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -212,8 +228,10 @@ def bench_c2(args):
         "data": "synthetic",
         "config": {"workload": "C2 batched decode: 512 micro-models, NCP* per axis in "
                                "{8,12,16,24,32}, degree in {2,3}, 64^3 voxels each, value + 3 "
-                               "gradients, FP32, one persistent launch replayed from a HIP graph",
+                               "gradients, FP32, one persistent launch replayed from a HIP "
+                               "graph, one 16-byte record per voxel",
                    "nblocks": batch.nblocks, "res": list(res), "channels": 4,
+                   "layout": "[block][x][y][z][value, d/du, d/dv, d/dw]",
                    "schedule": {"rows_per_item": plan.tune.rows_per_item,
                                 "waves": plan.tune.waves, "workgroups": plan.ngroups,
                                 "items": plan.nwork, "slab_floats": plan.tune.slab_floats,
@@ -224,6 +242,11 @@ def bench_c2(args):
                      "kernel": "decode_sep_kernel", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": ev_ms, "min_launch_ms": ev_min},
         "err_vs_fp64": err,
+        "planar": {"value": nvox / (planar_ms * 1e-3), "ms_per_step": planar_ms,
+                   "avg_launch_ms": planar_ev,
+                   "layout": "[block][channel][x][y][z]",
+                   "schedule": [pplan.tune.rows_per_item, pplan.tune.waves, pplan.ngroups,
+                                pplan.tune.slab_floats, pplan.tune.store]},
     }
     if not args.no_plain:
         pms, pev, _ = timed_steps(lambda: fa.decode_plain(m, res, 15, out=out),
@@ -240,7 +263,7 @@ def bench_c2(args):
                 g2, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dt, plan=pl, out=o2))
                 lms, lev, _ = timed_steps(g2.replay, args.steps, args.warmup, stream)
                 lp[f"{dt}_{kern}"] = {"value": nvox / (lms * 1e-3), "ms_per_step": lms,
-                                      "speedup_vs_f32": ms / lms,
+                                      "speedup_vs_f32_planar": planar_ms / lms,
                                       "err_vs_fp64": err_vs_oracle_decode(batch, o2, res)}
                 del o2, g2
         line["lowp"] = lp
@@ -847,25 +870,37 @@ def bench_c5(args):
     cands = [(r, w, gr, 0, 8192, st) for r in (8, 16) for w in (4, 8) for gr in (768, 1 << 20)
              for st in (0, 1)]
     variants = {}
-    for name, dtype, kernel in (("f32_valu", "f32", 0), ("bf16_mfma", "bf16", 1),
-                                ("f16_mfma", "f16", 1), ("bf16_valu", "bf16", 0),
-                                ("f16_valu", "f16", 0)):
+    # planar [block][channel][x][y][z] output, and (VALU kernel only) one
+    # 16-byte record per voxel
+    for name, dtype, kernel, inter in (("f32_valu", "f32", 0, 0), ("bf16_mfma", "bf16", 1, 0),
+                                       ("f16_mfma", "f16", 1, 0), ("bf16_valu", "bf16", 0, 0),
+                                       ("f16_valu", "f16", 0, 0),
+                                       ("f32_valu_interleaved", "f32", 0, 1),
+                                       ("bf16_valu_interleaved", "bf16", 0, 1)):
         m.lattice(dtype)
+        mk = 15 | fa.OUT_INTERLEAVED if inter else 15
         if kernel:
             plan = fa.Plan(m, res, kernel=1)
         else:
-            plan, _ = autotune.tune(m, res, 15, dtype, candidates=cands,
+            plan, _ = autotune.tune(m, res, mk, dtype, candidates=cands,
                                     use_cache=not args.retune)
-        graph, _ = fa.capture(lambda: fa.decode(m, res, 15, dtype=dtype, plan=plan, out=out))
+        graph, _ = fa.capture(lambda: fa.decode(m, res, mk, dtype=dtype, plan=plan, out=out))
         ms, ev_ms, _ = timed_steps(graph.replay, max(5, args.steps // 5), 2, stream)
+        del graph
         lat_b = (4 if dtype == "f32" else 2) * b.ctrl.size
+        # interleaved results are checked through a [block][x][y][z][4] view
+        chk = out.view((b.nblocks,) + res + (4,)) if inter else out
         variants[name] = {"value": nvox / (ms * 1e-3), "ms_per_step": ms,
                           "roofline": _roof(nvox * 16 + lat_b, ev_ms,
                                             "decode_mfma" if kernel else "decode_sep", "c5"),
-                          "err_vs_fp64": err_vs_oracle_decode(b, out, res, nsample=100000)}
+                          "err_vs_fp64": err_vs_oracle_decode(b, chk, res, nsample=100000,
+                                                              interleaved=bool(inter))}
     base = variants["f32_valu"]["ms_per_step"]
     for v in variants.values():
         v["speedup_vs_f32"] = base / v["ms_per_step"]
+    variants["bf16_valu_interleaved"]["speedup_vs_f32_interleaved"] = (
+        variants["f32_valu_interleaved"]["ms_per_step"] /
+        variants["bf16_valu_interleaved"]["ms_per_step"])
     best = variants["bf16_mfma"]
     line = _common(args, METRIC, best["value"], "voxels/s", best["ms_per_step"], "bf16",
                    "C5 precision: 4096 micro-models of 32^3 control points (k^-5/3), cubic, "
@@ -931,8 +966,10 @@ def probe(args):
         b = fi.config_c2() if w == "c2" else fi.config_c1()
         m = fa.MicroModels.from_batch(b)
         plan = fa.Plan(m, res, *args.probe_tune)
+        # C2 is timed in the interleaved layout, C1 in the planar one
+        mk = 15 | fa.OUT_INTERLEAVED if w == "c2" else 15
         out = torch.empty((b.nblocks, 4) + res, device="cuda")
-        run = lambda: fa.decode(m, res, 15, plan=plan, out=out)
+        run = lambda: fa.decode(m, res, mk, plan=plan, out=out)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()

@@ -67,6 +67,10 @@ typedef enum fa_dtype {
 #define FA_MAX_NCP 64
 #define FA_MAX_RES 256
 
+/* Decode output layout flag (OR-ed into fa_decode_blocks' mask with all
+ * four channels): one 16-byte record (value, d/du, d/dv, d/dw) per voxel. */
+#define FA_OUT_INTERLEAVED 0x100u
+
 /* Descriptor flag bits written by fa_validate_blocks. */
 #define FA_FLAG_UNIFORM_X 1u /* x knots are exactly (float)(j-p)/(float)(n-p) */
 #define FA_FLAG_UNIFORM_Y 2u
@@ -161,9 +165,13 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
  *   work, wg_off  device copies of a plan from fa_plan_decode made with
  *           the same tune and res, or both NULL for the default order
  *   ngroups workgroups in the plan (ignored when work is NULL)
- *   out     device FP32 [nblocks][popcount(mask)][res0][res1][res2]
+ *   out     device FP32 [nblocks][popcount(mask)][res0][res1][res2], or
+ *           with mask = 15 | FA_OUT_INTERLEAVED [nblocks][res0][res1][res2][4]
+ *           (the same values, one 16-byte record per voxel)
  * FA_ERR_UNSUPPORTED if tune->kernel selects the MFMA kernel with an FP32
- * lattice or with a tile other than 16 rows and 4 waves.
+ * lattice, with a tile other than 16 rows and 4 waves, or with the
+ * interleaved layout; FA_ERR_INVALID_ARG for FA_OUT_INTERLEAVED without all
+ * four channels.
  */
 fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
                            const void *ctrl, fa_dtype dtype, const int32_t res[3],

@@ -262,12 +262,18 @@ class Plan:
         self.res = tuple(int(r) for r in res)
 
 
+OUT_INTERLEAVED = 0x100  # FA_OUT_INTERLEAVED: one (value, d/du, d/dv, d/dw) record per voxel
+
+
 def decode(models, res, mask=15, dtype="f32", plan=None, tune=None, out=None, stream=None):
-    """Batched grid decode (fa_decode_blocks) -> [nb, nch, R0, R1, R2] float32."""
+    """Batched grid decode (fa_decode_blocks) -> [nb, nch, R0, R1, R2] float32,
+    or [nb, R0, R1, R2, 4] with mask = 15 | OUT_INTERLEAVED."""
     desc, ctrl = models.lattice(dtype, stream)
     if out is None:
-        out = torch.empty((models.nblocks, nch(mask)) + tuple(int(r) for r in res),
-                          dtype=torch.float32, device=models.device)
+        r = tuple(int(v) for v in res)
+        shape = ((models.nblocks,) + r + (4,) if mask & OUT_INTERLEAVED
+                 else (models.nblocks, nch(mask)) + r)
+        out = torch.empty(shape, dtype=torch.float32, device=models.device)
     if plan is not None:
         assert plan.res == tuple(int(r) for r in res)
         t, work, off, ng = plan.tune, _ptr(plan.work), _ptr(plan.wg_off), plan.ngroups

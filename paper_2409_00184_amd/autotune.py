@@ -16,7 +16,7 @@ import os
 import numpy as np
 import torch
 
-from . import Plan, decode
+from . import Plan, decode, nch
 
 CACHE = os.environ.get("FA_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "fa_tune.json"))
@@ -109,7 +109,8 @@ def tune(models, res, mask=15, dtype="f32", candidates=None, use_cache=True, ker
         c = cache[sig]["best"]
         return Plan(models, res, *c), [(tuple(c), cache[sig]["ms"])]
     cands = [c for c in (candidates or CANDIDATES) if c[3] in kernels]
-    out = torch.empty((models.nblocks, bin(mask).count("1")) + tuple(res), dtype=torch.float32,
+    # planar [nb][nch][res] or interleaved [nb][res][4]: the same number of floats
+    out = torch.empty((models.nblocks, nch(mask)) + tuple(res), dtype=torch.float32,
                       device=models.device)
     report = []
     best = None

@@ -245,8 +245,10 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
                            uint32_t mask, const fa_tune *tune, const fa_work *work,
                            const int32_t *wg_off, int32_t ngroups, float *out,
                            void *stream) {
-    if (!blocks || !knots || !ctrl || !out || nblocks <= 0 || !res_ok(res) ||
-        (mask & 15u) == 0 || (mask & ~15u) != 0)
+    const bool inter = (mask & FA_OUT_INTERLEAVED) != 0;
+    const uint32_t ch = mask & 15u;
+    if (!blocks || !knots || !ctrl || !out || nblocks <= 0 || !res_ok(res) || ch == 0 ||
+        (mask & ~(15u | FA_OUT_INTERLEAVED)) != 0 || (inter && ch != 15u))
         return FA_ERR_INVALID_ARG;
     if (dtype != FA_F32 && dtype != FA_BF16 && dtype != FA_F16) return FA_ERR_INVALID_ARG;
     if ((work == nullptr) != (wg_off == nullptr)) return FA_ERR_INVALID_ARG;
@@ -254,8 +256,10 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
-    const DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, dtype, res, mask, t, work,
-                                     wg_off, out);
+    if (inter && t.kernel == 1) return FA_ERR_UNSUPPORTED;
+    DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, dtype, res, ch, t, work, wg_off,
+                               out);
+    a.interleave = inter ? 1 : 0;
     int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
     hipError_t e;
     if (t.kernel == 1) e = launch_decode_mfma(a, t.waves, grid, (hipStream_t)stream);

@@ -88,7 +88,8 @@ __device__ __forceinline__ float comp(const float4 &v, int r) {
     return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
 }
 
-// MODE 0: decode, 1: residual form, 2: error form
+// MODE 0: decode, 1: residual form, 2: error form, 3: decode of all four
+// channels stored interleaved (one 16-byte record per voxel)
 template <int P, bool NT, int MODE>
 __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int col0, int64_t item,
                          SepSmem &sm) {
@@ -99,7 +100,7 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     const int64_t koff = B.knot_off, coff = B.ctrl_off;
     const float scale = B.scale;
     const int nkn = nx + ny + nz + 3 * (P + 1);
-    constexpr bool RESID = MODE != 0;  // reads the samples
+    constexpr bool RESID = MODE == 1 || MODE == 2;  // reads the samples
     constexpr bool GRAD = MODE == 1;   // stores the scaled residual
 
     lds_barrier();  // the previous item is done with the shared buffers
@@ -295,6 +296,14 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
                                                           gr, live ? off : kDead, 0, NT ? 2 : 0);
                 else
                     amax = fmaxf(amax, live ? fabsf(r) : 0.0f);
+            } else if (MODE == 3) {
+                if (live) {
+                    const f32x4 rec = {val, gx, gy, gz};
+                    f32x4 *o = reinterpret_cast<f32x4 *>(a.out) +
+                               ((int64_t)b * vox + (int64_t)u * plane_out + (int64_t)v * a.rz + w);
+                    if (NT) __builtin_nontemporal_store(rec, o);
+                    else *o = rec;
+                }
             } else if (live) {
                 float *o = ob + (int64_t)u * plane_out;
                 if (NT) {
@@ -512,6 +521,9 @@ hipError_t launch_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s)
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s) {
     if (a.samples && a.errs) return launch_sep<false, 2>(a, waves, grid, s);
+    if (a.interleave)
+        return a.nt_store ? launch_sep<true, 3>(a, waves, grid, s)
+                          : launch_sep<false, 3>(a, waves, grid, s);
     if (a.samples)
         return a.nt_store ? launch_sep<true, 1>(a, waves, grid, s)
                           : launch_sep<false, 1>(a, waves, grid, s);

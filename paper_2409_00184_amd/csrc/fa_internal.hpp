@@ -40,6 +40,9 @@ struct DecodeLaunch {
     // max |f - samples| and FP64 sum of squares into partials[2 item + {0,1}]
     float *errs;
     int64_t errs_stride;
+    // decode form: all four channels stored as one 16-byte record per voxel,
+    // out = [block][u][v][w][4]
+    int interleave;
 };
 
 hipError_t launch_decode_sep(const DecodeLaunch &a, int waves, int grid, hipStream_t s);

@@ -120,3 +120,50 @@ def test_decode_c2_full(fa):
     ti = torch.as_tensor(idx, device="cuda").long()
     got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
     check_elementwise_bound(got, r, S, 64.0, "C2 sampled")
+
+
+@pytest.mark.parametrize("res", [(17, 23, 29), (64, 64, 64), (2, 2, 2)])
+@pytest.mark.parametrize("sched", [None, (4, 2, 5), (16, 8, 0)])
+def test_decode_interleaved_matches_planar(fa, res, sched):
+    """mask 15 | OUT_INTERLEAVED stores the planar decode's values as one
+    (value, d/du, d/dv, d/dw) record per voxel, bit for bit."""
+    say("decode interleaved", res, sched)
+    b = mixed_batch(26, 19, ncp_hi=40)
+    m = models(b)
+    plan = None if sched is None else fa.Plan(m, res, rows=sched[0], waves=sched[1],
+                                              grid=sched[2])
+    planar = fa.decode(m, res, 15, plan=plan)
+    inter = torch.full((b.nblocks,) + res + (4,), float("nan"), device="cuda")
+    fa.decode(m, res, 15 | fa.OUT_INTERLEAVED, plan=plan, out=inter)
+    assert torch.equal(inter, planar.permute(0, 2, 3, 4, 1)), "same values, other layout"
+    ref = oracle.decode_blocks(oracle_blocks(b), res, 15)
+    check_normwise(inter.permute(0, 4, 1, 2, 3).cpu().numpy(), ref, 1e-5, f"interleaved {res}")
+
+
+def test_decode_interleaved_c2_sampled(fa):
+    """C2 at full size in the interleaved layout (the bench's form):
+    sampled voxels within the FP32 elementwise bound of the oracle."""
+    say("decode interleaved C2")
+    b = fi.config_c2()
+    m = models(b)
+    res = (64, 64, 64)
+    out = torch.full((b.nblocks,) + res + (4,), float("nan"), device="cuda")
+    fa.decode(m, res, 15 | fa.OUT_INTERLEAVED, plan=fa.Plan(m, res), out=out)
+    assert not torch.isnan(out).any()
+    g = fi.rng(27)
+    n = 100000
+    idx = np.stack([g.integers(0, b.nblocks, n), g.integers(0, 64, n), g.integers(0, 64, n),
+                    g.integers(0, 64, n)], 1).astype(np.int32)
+    r, S = oracle.decode_samples(oracle_blocks(b), res, idx, with_abs=True)
+    ti = torch.as_tensor(idx, device="cuda").long()
+    got = out[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
+    check_elementwise_bound(got, r, S, 64.0, "C2 interleaved sampled")
+
+
+def test_decode_interleaved_rejected_on_matrix_cores(fa):
+    b = mixed_batch(28, 2)
+    m = models(b)
+    m.lattice("bf16")
+    with pytest.raises(Exception):
+        fa.decode(m, (16, 64, 64), 15 | fa.OUT_INTERLEAVED, dtype="bf16",
+                  tune=fa.FATune(0, 0, 0, 1, 0, 0))
