@@ -870,13 +870,14 @@ def bench_c5(args):
     cands = [(r, w, gr, 0, 8192, st) for r in (8, 16) for w in (4, 8) for gr in (768, 1 << 20)
              for st in (0, 1)]
     variants = {}
-    # planar [block][channel][x][y][z] output, and (VALU kernel only) one
-    # 16-byte record per voxel
+    # planar [block][channel][x][y][z] output, and one 16-byte record per voxel
     for name, dtype, kernel, inter in (("f32_valu", "f32", 0, 0), ("bf16_mfma", "bf16", 1, 0),
                                        ("f16_mfma", "f16", 1, 0), ("bf16_valu", "bf16", 0, 0),
                                        ("f16_valu", "f16", 0, 0),
                                        ("f32_valu_interleaved", "f32", 0, 1),
-                                       ("bf16_valu_interleaved", "bf16", 0, 1)):
+                                       ("bf16_valu_interleaved", "bf16", 0, 1),
+                                       ("bf16_mfma_interleaved", "bf16", 1, 1),
+                                       ("f16_mfma_interleaved", "f16", 1, 1)):
         m.lattice(dtype)
         mk = 15 | fa.OUT_INTERLEAVED if inter else 15
         if kernel:
@@ -898,9 +899,9 @@ def bench_c5(args):
     base = variants["f32_valu"]["ms_per_step"]
     for v in variants.values():
         v["speedup_vs_f32"] = base / v["ms_per_step"]
-    variants["bf16_valu_interleaved"]["speedup_vs_f32_interleaved"] = (
-        variants["f32_valu_interleaved"]["ms_per_step"] /
-        variants["bf16_valu_interleaved"]["ms_per_step"])
+    for k in ("bf16_valu_interleaved", "bf16_mfma_interleaved", "f16_mfma_interleaved"):
+        variants[k]["speedup_vs_f32_interleaved"] = (
+            variants["f32_valu_interleaved"]["ms_per_step"] / variants[k]["ms_per_step"])
     best = variants["bf16_mfma"]
     line = _common(args, METRIC, best["value"], "voxels/s", best["ms_per_step"], "bf16",
                    "C5 precision: 4096 micro-models of 32^3 control points (k^-5/3), cubic, "

@@ -169,9 +169,8 @@ fa_status fa_plan_decode(const fa_block *blocks, int32_t nblocks, const int32_t 
  *           with mask = 15 | FA_OUT_INTERLEAVED [nblocks][res0][res1][res2][4]
  *           (the same values, one 16-byte record per voxel)
  * FA_ERR_UNSUPPORTED if tune->kernel selects the MFMA kernel with an FP32
- * lattice, with a tile other than 16 rows and 4 waves, or with the
- * interleaved layout; FA_ERR_INVALID_ARG for FA_OUT_INTERLEAVED without all
- * four channels.
+ * lattice or with a tile other than 16 rows and 4 waves; FA_ERR_INVALID_ARG
+ * for FA_OUT_INTERLEAVED without all four channels.
  */
 fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float *knots,
                            const void *ctrl, fa_dtype dtype, const int32_t res[3],

@@ -256,7 +256,6 @@ fa_status fa_decode_blocks(const fa_block *blocks, int32_t nblocks, const float 
     if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
     const Tune t = resolve(tune);
     if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
-    if (inter && t.kernel == 1) return FA_ERR_UNSUPPORTED;
     DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, dtype, res, ch, t, work, wg_off,
                                out);
     a.interleave = inter ? 1 : 0;

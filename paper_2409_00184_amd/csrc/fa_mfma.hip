@@ -31,7 +31,9 @@
 // the item's 16 rows x 64 columns, so that every store instruction writes
 // four whole 256-byte z rows (a quarter wave per row): quarter rows stored
 // by different waves reach L2 at different times and were measured at 3.6
-// against 5.7 TB/s for whole rows.
+// against 5.7 TB/s for whole rows.  With interleaved output (one 16-byte
+// record per voxel) the same LDS tile holds the item's 16 x 64 records
+// instead, and each store instruction writes one whole z row (1 KB).
 // Items the tile does not take (NCP_z > 32, or a y window of more than 16
 // lattice rows) are decoded voxel by voxel by the same workgroup.
 //
@@ -131,7 +133,8 @@ __device__ __forceinline__ void dense_frag(const float (&N)[P + 1], int s, int k
 // the per-x-position table and the knots.
 struct MSmem {
     u32x4 *frag;
-    f32x4v *tile;  // [channel][row 16][16 groups of 4 columns], group ^ row
+    f32x4v *tile;  // [channel][row 16][16 groups of 4 columns], group ^ row;
+                   // interleaved: [row 16][64 column records], column ^ row
     float4 *xB;  // scale * Bx in ring order
     float4 *xD;  // scale * Dx in ring order
     int *xS;     // span along x
@@ -161,7 +164,7 @@ __device__ __forceinline__ MSmem mcarve(void *base, int rx) {
 }
 
 // Voxel-by-voxel decode of one item (items the tile does not take).
-template <int P>
+template <int P, bool INTER>
 __device__ void direct_item(const DecodeLaunch &a, const fa_block &B, int b, int row0, int nrows,
                             int col0) {
     const int nx = B.ncp[0], ny = B.ncp[1], nz = B.ncp[2];
@@ -202,14 +205,20 @@ __device__ void direct_item(const DecodeLaunch &a, const fa_block &B, int b, int
                 r[3] = fmaf(xB[i] * yB[j], tD, r[3]);
             }
         }
-        float *o = a.out + (int64_t)b * a.nch * vox + ((int64_t)u * a.ry + v) * a.rz + w;
+        const int64_t vi = ((int64_t)u * a.ry + v) * a.rz + w;
+        if constexpr (INTER) {
+            const f32x4v rec = {r[0], r[1], r[2], r[3]};
+            reinterpret_cast<f32x4v *>(a.out)[(int64_t)b * vox + vi] = rec;
+            continue;
+        }
+        float *o = a.out + (int64_t)b * a.nch * vox + vi;
         int c = 0;
         for (int ch = 0; ch < 4; ++ch)
             if ((a.mask >> ch) & 1u) o[(int64_t)(c++) * vox] = r[ch];
     }
 }
 
-template <int DT, int P>
+template <int DT, int P, bool INTER>
 __device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int row0, int nrows,
                           int col0, const MSmem &sm) {
     const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
@@ -225,7 +234,7 @@ __device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int r
     const int jlo = span_search(ny, P, ty, grid_pos(row0, a.ry)) - P;
     const int jhi = span_search(ny, P, ty, grid_pos(row0 + nrows - 1, a.ry));
     if (nz > kK || jhi - jlo + 1 > kJ) {
-        direct_item<P>(a, B, b, row0, nrows, col0);
+        direct_item<P, INTER>(a, B, b, row0, nrows, col0);
         return;
     }
 
@@ -333,6 +342,14 @@ __device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int r
         make_rsrc(a.out + (int64_t)b * a.nch * vox, (uint32_t)a.nch * vox * 4u);
     const uint32_t plane_b = (uint32_t)a.ry * (uint32_t)a.rz * 4u;
     uint32_t vo = ((uint32_t)(row0 + srow) * (uint32_t)a.rz + (uint32_t)ws) * 4u;
+    // interleaved: this lane writes records (l16, 16q + 4g + r) at column
+    // slot col ^ l16 (the 16 lanes of a row group hit 16 bank groups), and
+    // wave q stores rows 4q .. 4q+3, lane = column, 16 bytes each
+    const __amdgpu_buffer_rsrc_t irc =
+        make_rsrc(reinterpret_cast<f32x4v *>(a.out) + (int64_t)b * vox, vox * 16u);
+    const bool iok = col0 + lane < a.rz;
+    uint32_t io = ((uint32_t)row0 * (uint32_t)a.rz + (uint32_t)(col0 + lane)) * 16u;
+    const uint32_t irow_b = (uint32_t)a.rz * 16u, iplane_b = (uint32_t)a.ry * irow_b;
     uint32_t choff[4];
     {
         uint32_t c = 0;
@@ -407,6 +424,28 @@ __device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int r
             o[3][r] = gz;
         }
         lds_barrier();  // every wave is done reading the previous tile
+        if constexpr (INTER) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const f32x4v rec = {o[0][r], o[1][r], o[2][r], o[3][r]};
+                sm.tile[l16 * 64 + ((16 * q + 4 * g + r) ^ l16)] = rec;
+            }
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int row = 4 * q + k;
+                const f32x4v t = sm.tile[row * 64 + (lane ^ row)];
+                if (row < nrows && iok) {
+                    uint32_t d[4];
+                    __builtin_memcpy(d, &t, 16);
+                    const u32x4 dv = {d[0], d[1], d[2], d[3]};
+                    __builtin_amdgcn_raw_buffer_store_b128(dv, irc, io + (uint32_t)row * irow_b,
+                                                           0, kCpol);
+                }
+            }
+            io += iplane_b;
+            continue;
+        }
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch)
             if ((a.mask >> ch) & 1u) sm.tile[ch * 256 + wslot] = o[ch];
@@ -436,7 +475,7 @@ __device__ void mfma_item(const DecodeLaunch &a, const fa_block &B, int b, int r
     }
 }
 
-template <int DT>
+template <int DT, bool INTER>
 __global__ __launch_bounds__(256) void decode_mfma_kernel(DecodeLaunch a) {
     extern __shared__ float4 dyn_lds[];
     const MSmem sm = mcarve(dyn_lds, a.rx);
@@ -469,9 +508,9 @@ __global__ __launch_bounds__(256) void decode_mfma_kernel(DecodeLaunch a) {
         }
         const fa_block &B = a.blocks[b];
         const int p = B.degree[0];
-        if (p == 3) mfma_item<DT, 3>(a, B, b, row0, nrows, col0, sm);
-        else if (p == 2) mfma_item<DT, 2>(a, B, b, row0, nrows, col0, sm);
-        else mfma_item<DT, 1>(a, B, b, row0, nrows, col0, sm);
+        if (p == 3) mfma_item<DT, 3, INTER>(a, B, b, row0, nrows, col0, sm);
+        else if (p == 2) mfma_item<DT, 2, INTER>(a, B, b, row0, nrows, col0, sm);
+        else mfma_item<DT, 1, INTER>(a, B, b, row0, nrows, col0, sm);
     }
 }
 
@@ -481,10 +520,17 @@ hipError_t launch_decode_mfma(const DecodeLaunch &d, int waves, int grid, hipStr
     if ((d.dtype != FA_BF16 && d.dtype != FA_F16) || d.rows != kRows || waves != 4)
         return hipErrorNotSupported;
     const size_t lds = mfma_lds_bytes(d.rx);
-    if (d.dtype == FA_BF16)
-        hipLaunchKernelGGL(decode_mfma_kernel<FA_BF16>, dim3(grid), dim3(256), lds, s, d);
-    else
-        hipLaunchKernelGGL(decode_mfma_kernel<FA_F16>, dim3(grid), dim3(256), lds, s, d);
+    if (d.dtype == FA_BF16) {
+        if (d.interleave)
+            hipLaunchKernelGGL((decode_mfma_kernel<FA_BF16, true>), dim3(grid), dim3(256), lds, s, d);
+        else
+            hipLaunchKernelGGL((decode_mfma_kernel<FA_BF16, false>), dim3(grid), dim3(256), lds, s, d);
+    } else {
+        if (d.interleave)
+            hipLaunchKernelGGL((decode_mfma_kernel<FA_F16, true>), dim3(grid), dim3(256), lds, s, d);
+        else
+            hipLaunchKernelGGL((decode_mfma_kernel<FA_F16, false>), dim3(grid), dim3(256), lds, s, d);
+    }
     return hipGetLastError();
 }
 

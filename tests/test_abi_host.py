@@ -195,9 +195,6 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
                               vp, None) == 1
     assert L.fa_decode_blocks(vp, 1, vp, vp, 0, r, 15 | 0x200, None, None, None, 0, vp,
                               None) == 1
-    mt = fa.FATune(0, 0, 0, 1, 0, 0)  # the matrix-core kernel writes the planar layout only
-    assert L.fa_decode_blocks(vp, 1, vp, vp, 1, r, 15 | fa.OUT_INTERLEAVED, ctypes.byref(mt),
-                              None, None, 0, vp, None) == 2
     assert L.fa_query_points(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),
                              fa._f32x3((1, 0, 1)), vp, vp, 0, vp, 5, 15, vp, None) == 1
     assert L.fa_query_rays(vp, 1, vp, fa._i32x3((1, 1, 1)), fa._f32x3((0, 0, 0)),

@@ -159,11 +159,3 @@ def test_decode_interleaved_c2_sampled(fa):
     got = out[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
     check_elementwise_bound(got, r, S, 64.0, "C2 interleaved sampled")
 
-
-def test_decode_interleaved_rejected_on_matrix_cores(fa):
-    b = mixed_batch(28, 2)
-    m = models(b)
-    m.lattice("bf16")
-    with pytest.raises(Exception):
-        fa.decode(m, (16, 64, 64), 15 | fa.OUT_INTERLEAVED, dtype="bf16",
-                  tune=fa.FATune(0, 0, 0, 1, 0, 0))

@@ -153,3 +153,31 @@ def test_c5_sampled(fa):
         else:
             _bound_check(got, ref, S, 6.0, ULP[dtype], f"C5 {dtype}")
     del out
+
+
+def _fallback_batch():
+    g = fi.rng(57)
+    ncp = [(40, 8, 8), (8, 48, 12), (6, 6, 33), (9, 7, 31), (12, 17, 5), (5, 6, 32)]
+    deg = [(3, 3, 3), (2, 2, 2), (1, 1, 1), (3, 3, 3), (2, 2, 2), (1, 1, 1)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    return fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("batch", ["mixed", "fallback"])
+def test_lowp_interleaved_matches_planar(fa, kernel, dtype, batch):
+    """Interleaved records (mask 15 | OUT_INTERLEAVED) hold the planar
+    decode's values bit for bit, on the matrix-core kernel (tile and
+    voxel-by-voxel items, partial row bands and column tiles) and on the
+    VALU kernel with 2-byte lattices."""
+    say("lowp interleaved", kernel, dtype, batch)
+    b = (mixed_batch(58, 9, ncp_lo=4, ncp_hi=32, nonuniform=0.3) if batch == "mixed"
+         else _fallback_batch())
+    m = models(b)
+    for res in [(64, 64, 64), (23, 17, 41), (9, 21, 150)]:
+        plan = fa.Plan(m, res, kernel=kernel) if kernel else fa.Plan(m, res)
+        planar = fa.decode(m, res, 15, dtype=dtype, plan=plan)
+        inter = torch.full((b.nblocks,) + res + (4,), float("nan"), device="cuda")
+        fa.decode(m, res, 15 | fa.OUT_INTERLEAVED, dtype=dtype, plan=plan, out=inter)
+        assert torch.equal(inter, planar.permute(0, 2, 3, 4, 1)), res
