@@ -215,3 +215,35 @@ def test_adjoint_leaves_padding(fa):
         o = int(b.ctrl_off[bb])
         inside[o:o + int(np.prod(b.ncp[bb]))] = True
     assert np.all(G[~inside] == 7.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_query_lattice_beyond_4gb(fa, dtype):
+    """Blocks whose lattice lies past the first 4 GB of the lattice array
+    (element offsets beyond 32-bit byte range) give bit for bit the values
+    of the same blocks near its start, for points spread over several
+    blocks per wave."""
+    import copy
+    say("query far lattice", dtype)
+    nb = (2, 2, 2)
+    b = mixed_batch(35, 8, ncp_lo=4, ncp_hi=24)
+    near = models(b)
+    far = copy.copy(near)
+    F = 1 << 30  # elements: 4 GB of FP32 before the first block
+    hd = near.host_desc.copy()
+    hd["ctrl_off"] += F
+    far.host_desc = hd
+    far.desc = torch.from_numpy(hd.view(np.uint8).copy()).cuda()
+    big = torch.zeros(F + near.ctrl.numel(), dtype=torch.float32, device="cuda")
+    big[F:] = near.ctrl
+    far.ctrl, far.ctrl_lp, far.desc_lp = big, {}, {}
+    boc = np.arange(8, dtype=np.int32)
+    bocd = torch.as_tensor(boc, device="cuda")
+    g = fi.rng(36)
+    xyz = torch.as_tensor(g.uniform(0, 1, (200000, 3)).astype(np.float32), device="cuda")
+    o, e = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    rn = fa.query(near, xyz, nb, o, e, bocd, dtype=dtype)
+    rf = fa.query(far, xyz, nb, o, e, bocd, dtype=dtype)
+    assert torch.equal(rn, rf)
+    del big, far
+    torch.cuda.empty_cache()
