@@ -384,6 +384,26 @@ def bench_c3(args):
                               for k, v in orders.items()},
                     "timed_order": best,
                     "err_vs_fp64": err})
+    if not args.no_lowp:
+        # 2-byte lattices (P / s_b with the per-block max-abs scale), the
+        # ray-tile order; errors against the FP64 oracle of the FP32 lattice
+        lp = {}
+        for dt in ("bf16", "f16"):
+            m.lattice(dt)
+            fn = lambda: fa.query_rays(m, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0),
+                                       (1, 1, 1), boc, dtype=dt, out=out)
+            graph, _ = fa.capture(fn)
+            lms, lev, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+            del graph
+            fn()
+            torch.cuda.synchronize()
+            g2 = out[idx].double().cpu().numpy()
+            lp[dt] = {"value": n / (lms * 1e-3), "ms_per_step": lms, "avg_launch_ms": lev,
+                      "speedup_vs_f32": ms / lms,
+                      "err_vs_fp64": {k: float(np.abs(g2[:, c] - ref[:, c]).max() /
+                                               np.abs(ref[:, c]).max())
+                                      for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}}
+        line["lowp"] = lp
     if not args.no_cpu_baseline:
         th = oracle.nthreads_default()
         t0 = time.perf_counter()
