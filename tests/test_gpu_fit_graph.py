@@ -278,3 +278,22 @@ def test_autotune_picks_valid_schedule(fa, tmp_path, monkeypatch):
     assert torch.equal(a, ref)
     plan2, rep2 = autotune.tune(m, res, 15, "f32")  # from the cache
     assert len(rep2) == 1 and plan2.tune.rows_per_item == plan.tune.rows_per_item
+
+
+def test_autotune_interleaved_layout(fa, tmp_path, monkeypatch):
+    """The autotuner times the interleaved-record layout through its own
+    cache entry; its schedule decodes the same records as the default."""
+    say("autotune interleaved")
+    from paper_2409_00184_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    b = mixed_batch(64, 24, ncp_hi=32)
+    m = models(b)
+    res = (32, 24, 64)
+    mk = 15 | fa.OUT_INTERLEAVED
+    plan, report = autotune.tune(m, res, mk, "f32", candidates=autotune.CANDIDATES[:4])
+    assert len(report) == 4
+    assert autotune.signature(m, res, mk, "f32") != autotune.signature(m, res, 15, "f32")
+    a = fa.decode(m, res, mk, plan=plan)
+    assert a.shape == (b.nblocks,) + res + (4,)
+    assert torch.equal(a, fa.decode(m, res, mk))
+    assert torch.equal(a, fa.decode(m, res, 15).permute(0, 2, 3, 4, 1))
