@@ -159,3 +159,53 @@ def test_decode_interleaved_c2_sampled(fa):
     got = out[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
     check_elementwise_bound(got, r, S, 64.0, "C2 interleaved sampled")
 
+
+
+@pytest.mark.parametrize("layout", ["planar", "interleaved"])
+def test_decode_maximum_resolution(fa, layout):
+    """Grids of FA_MAX_RES = 256 per axis and lattices of FA_MAX_NCP = 64 per
+    axis: every voxel written (NaN fill), sampled voxels within the FP32
+    elementwise bound of the oracle."""
+    say("decode max res", layout)
+    g = fi.rng(29)
+    ncp = [(64, 64, 64), (2, 2, 2), (33, 64, 5)]
+    deg = [(3, 3, 3), (1, 1, 1), (2, 2, 2)]
+    kl = [[fi.clamped_uniform_knots(n[a], p[0]) for a in range(3)] for n, p in zip(ncp, deg)]
+    b = fi.pack(ncp, deg, kl, [g.normal(size=n) for n in ncp])
+    m = models(b)
+    res = (256, 256, 256)
+    if layout == "planar":
+        out = torch.full((b.nblocks, 4) + res, float("nan"), device="cuda")
+        fa.decode(m, res, 15, plan=fa.Plan(m, res), out=out)
+    else:
+        out = torch.full((b.nblocks,) + res + (4,), float("nan"), device="cuda")
+        fa.decode(m, res, 15 | fa.OUT_INTERLEAVED, plan=fa.Plan(m, res), out=out)
+    assert not torch.isnan(out).any()
+    n = 60000
+    idx = np.stack([g.integers(0, b.nblocks, n), g.integers(0, 256, n), g.integers(0, 256, n),
+                    g.integers(0, 256, n)], 1).astype(np.int32)
+    idx[:8, 1:] = [[0, 0, 0], [255, 255, 255], [0, 255, 0], [255, 0, 255],
+                   [128, 1, 254], [1, 128, 0], [255, 255, 0], [0, 0, 255]]
+    r, S = oracle.decode_samples(oracle_blocks(b), res, idx, with_abs=True)
+    ti = torch.as_tensor(idx, device="cuda").long()
+    if layout == "planar":
+        got = out[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
+    else:
+        got = out[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].cpu().numpy()
+    check_elementwise_bound(got, r, S, 64.0, f"max res {layout}")
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_query_empty_input(fa):
+    """Zero points: the call returns without a launch and leaves the output
+    untouched."""
+    say("query empty")
+    b = mixed_batch(30, 2)
+    m = models(b)
+    xyz = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    out = torch.full((1, 4), 7.0, device="cuda")
+    fa.query(m, xyz, (1, 1, 2), (0, 0, 0), (1, 1, 1),
+             torch.as_tensor(np.arange(2, dtype=np.int32), device="cuda"), out=out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
