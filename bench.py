@@ -838,12 +838,11 @@ def bench_c4(args):
     ms, ev_ms, _ = timed_steps(lambda: losses.append(it()), args.steps, args.warmup, stream)
     first, last = float(losses[0]), float(losses[-1])
     ms_t = timed_steps(it_torch, args.steps, args.warmup, stream)[0]
-    # the same iteration captured into one HIP graph (capturable Adam); every
-    # replay does the whole iteration's work.  The iteration is bound by its
-    # kernels' HBM traffic, not by launches, so the graph is not faster
+    # the same iteration captured into one HIP graph (the same fused Adam,
+    # capturable); every replay does the whole iteration's work
     mg = fa.MicroModels.from_batch(b)
     ctrl_g = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
-    opt_g = torch.optim.Adam([ctrl_g], lr=0.05, capturable=True)
+    opt_g = torch.optim.Adam([ctrl_g], lr=0.05, fused=True, capturable=True)
     graph, loss_g = fa.capture_fit_step(ctrl_g, opt_g, mg, res, yf, fa.Plan(mg, res))
     ms_g = timed_steps(graph.replay, args.steps, args.warmup, stream)[0]
     loss_graph = float(loss_g)

@@ -687,15 +687,18 @@ class FAFitMSE(torch.autograd.Function):
 
 
 def capture_fit_step(ctrl, opt, models, res, y, plan=None, warmup=3):
-    """One fit iteration -- zero_grad, FAFitMSE forward (value decode and
-    fused residual/loss/cotangent), the adjoint in backward, opt.step() --
+    """One fit iteration -- FAFitMSE forward (value decode and fused
+    residual/loss/cotangent), the adjoint in backward, opt.step() --
     captured into a HIP graph, so that a fit loop is one graph launch per
-    iteration.  `opt` must be capturable (e.g. Adam(..., capturable=True));
-    `warmup` eager iterations run first on a side stream (they are real
-    steps of the fit).  Returns (graph, loss): every replay performs one
-    more iteration and overwrites the static `loss` tensor."""
+    iteration.  The gradient is set by the adjoint (it writes every control
+    point), not accumulated into a zeroed buffer: inside the capture it is a
+    tensor of the graph's pool that every replay rewrites.  `opt` must be
+    capturable (e.g. Adam(..., capturable=True), or fused=True for one
+    update kernel); `warmup` eager iterations run first on a side stream
+    (they are real steps of the fit).  Returns (graph, loss): every replay
+    performs one more iteration and overwrites the static `loss` tensor."""
     def step():
-        opt.zero_grad(set_to_none=False)
+        opt.zero_grad(set_to_none=True)
         loss = FAFitMSE.apply(ctrl, models, res, y, plan)
         loss.backward()
         opt.step()

@@ -220,12 +220,14 @@ def test_graph_replay_matches_eager(fa):
         _ = (out * 2).sum().item()  # eager work between replays
 
 
-def test_captured_fit_step_matches_eager(fa):
-    """A whole fit iteration (decode, fused MSE, adjoint, capturable Adam)
-    captured into one graph: every replay, with eager work and
-    synchronisation in between, moves the lattice exactly as an eager
-    iteration from the same state does."""
-    say("captured fit step")
+@pytest.mark.parametrize("adam", ["capturable", "fused"])
+def test_captured_fit_step_matches_eager(fa, adam):
+    """A whole fit iteration (decode, fused MSE, adjoint, capturable Adam:
+    multi-kernel or fused) captured into one graph: every replay, with eager
+    work and synchronisation in between, moves the lattice exactly as an
+    eager iteration from the same state does (the eager one accumulates into
+    a zeroed gradient, the graph sets it)."""
+    say("captured fit step", adam)
     b = mixed_batch(64, 6, ncp_lo=4, ncp_hi=14)
     res = (24, 20, 28)
     g = fi.rng(65)
@@ -235,7 +237,7 @@ def test_captured_fit_step_matches_eager(fa):
     for _ in range(2):
         m = models(b)
         ctrl = P0.clone().requires_grad_(True)
-        opt = torch.optim.Adam([ctrl], lr=0.05, capturable=True)
+        opt = torch.optim.Adam([ctrl], lr=0.05, capturable=True, fused=(adam == "fused"))
         runs.append((m, ctrl, opt, fa.Plan(m, res)))
     me, ce, oe, pe = runs[0]
     mg, cg, og, pg = runs[1]
