@@ -299,7 +299,11 @@ def bench_c1(args):
     res = (64, 64, 64)
     batch = fi.config_c1()
     m = fa.MicroModels.from_batch(batch)
-    plan, _ = autotune.tune(m, res, 15, "f32", use_cache=not args.retune)
+    # one block: items of one or two y rows give more workgroups than the
+    # batch schedules do
+    cands = list(autotune.CANDIDATES) + [(r, w, 1 << 20, 0, 8192, st) for r in (1, 2)
+                                         for w in (1, 2) if w <= r for st in (0, 1)]
+    plan, _ = autotune.tune(m, res, 15, "f32", candidates=cands, use_cache=not args.retune)
     out = torch.empty((1, 4) + res, device="cuda")
     graph, _ = fa.capture(lambda: fa.decode(m, res, 15, plan=plan, out=out))
     ms, ev_ms, _ = timed_steps(graph.replay, args.steps, args.warmup,
