@@ -61,12 +61,13 @@ def source_hash(kernel):
     return h.hexdigest()[:12]
 
 
-def traffic_from_profiles(kernel, workload):
+def traffic_from_profiles(kernel, workload, profiles=None):
     """HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and
     WRITE_SIZE (scaled by the copy-kernel calibration), from
     profiles/<kernel>_<workload>_traffic.json, if taken on this exact kernel
     source; else None."""
-    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    p = os.path.join(profiles or os.path.join(ROOT, "profiles"),
+                     f"{kernel}_{workload}_traffic.json")
     try:
         with open(p) as f:
             t = json.load(f)

@@ -467,7 +467,9 @@ fa_status fa_visible_cells(const fa_ray *rays, int32_t width, int32_t height, in
  * 1), then the NCP^3 FP32 control points [x][y][z].  A record therefore
  * takes exactly 1 + ((NCP + p) * 3 + NCP^3) * 4 bytes, and NCP is recovered
  * from its size.  One NCP and one degree per block (as Eq. 2 counts them):
- * blocks with unequal NCP or degree per axis are FA_ERR_INVALID_ARG.
+ * blocks with unequal NCP or degree per axis are FA_ERR_INVALID_ARG, and so
+ * are knot vectors that are not clamped on [0, 1] and non-decreasing;
+ * degree > FA_MAX_DEGREE or NCP > FA_MAX_NCP is FA_ERR_UNSUPPORTED.
  *   blocks, knots, ctrl  host arrays (FP32 lattices)
  * FA_ERR_DEVICE on an I/O error.
  */
@@ -489,7 +491,9 @@ typedef struct fa_store_stats {
  * large enough for the file's largest record).  With FA_STORE_PINNED the
  * slots are page-locked (hipHostMalloc) so staging copies are DMA
  * transfers.  Allocates; not for hot loops.  FA_ERR_INVALID_ARG for a
- * missing or malformed file.
+ * missing or malformed file (bad header, a record outside the file or of a
+ * size no NCP gives); FA_ERR_UNSUPPORTED for a record of degree >
+ * FA_MAX_DEGREE.
  */
 fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, fa_store **out);
 fa_status fa_store_close(fa_store *s);
@@ -504,7 +508,12 @@ fa_status fa_store_info(const fa_store *s, int32_t *nblocks, int32_t *ncp, int32
  * slot of the least recently used block.  slots[i] (may be null) receives
  * the slot holding ids[i] at the time it was looked up (a later lookup in
  * the same call can evict it when n exceeds the cache).  stats (may be null)
- * receives the running counters.
+ * receives the running counters.  Waits first for the copies of a previous
+ * fa_store_stage on this store (they read slots a refill would overwrite).
+ * A record is read and checked before the cache changes: FA_ERR_DEVICE for
+ * a read error, FA_ERR_INVALID_ARG for knots that are not clamped and
+ * non-decreasing; the blocks before it in ids stay cached and the cache is
+ * otherwise unchanged.
  */
 fa_status fa_store_fetch(fa_store *s, const int32_t *ids, int32_t n, int32_t *slots,
                          fa_store_stats *stats);

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <fcntl.h>
+#include <sys/stat.h>
 #include <unistd.h>
 
 #include <algorithm>
@@ -64,6 +65,19 @@ bool read_at(int fd, void *dst, int64_t n, int64_t off) {
     return true;
 }
 
+// A clamped knot vector of a record (n + p stored values, the last knot 1
+// implicit): p + 1 leading zeros, p trailing stored ones, finite and
+// non-decreasing -- the rules fa_validate_blocks applies to a batch.
+bool knots_ok(const float *t, int n, int p) {
+    for (int j = 0; j <= p; ++j)
+        if (t[j] != 0.0f) return false;
+    for (int j = n; j < n + p; ++j)
+        if (t[j] != 1.0f) return false;
+    for (int j = 1; j < n + p; ++j)
+        if (!(t[j] >= t[j - 1]) || !(t[j] <= 1.0f)) return false;
+    return true;
+}
+
 int64_t align64(int64_t v) { return (v + 63) / 64 * 64; }
 int64_t knot_span(int n, int p) { return (3 * (int64_t)(n + p + 1) + 3) / 4 * 4; }
 
@@ -92,13 +106,25 @@ struct fa_store {
 
 namespace {
 
-// Ensure block b is cached; returns its slot or -1 on an I/O or format error.
+// Ensure block b is cached; returns its slot, kReadError on an I/O error or
+// kFormatError for a record whose knots are not clamped and non-decreasing.
+// The record is read and checked before the cache is touched, so a failure
+// leaves the cache (slots, recency, counters) as it was.
+constexpr int32_t kReadError = -1, kFormatError = -2;
+
 int32_t fetch_one(fa_store *s, int32_t b) {
     int32_t slot = s->slot_of_block[b];
     if (slot >= 0) {
         s->stats.hits++;
         s->lru.splice(s->lru.begin(), s->lru, s->where[slot]);
         return slot;
+    }
+    const int n = s->ncp[b], p = s->deg[b];
+    if (!read_at(s->fd, s->raw.data(), s->size[b], s->off[b])) return kReadError;
+    for (int a = 0; a < 3; ++a) {
+        float t[FA_MAX_NCP + FA_MAX_DEGREE];
+        std::memcpy(t, s->raw.data() + 1 + (size_t)a * (n + p) * 4, (size_t)(n + p) * 4);
+        if (!knots_ok(t, n, p)) return kFormatError;
     }
     s->stats.misses++;
     if ((int32_t)s->lru.size() < s->capacity) {
@@ -108,11 +134,9 @@ int32_t fetch_one(fa_store *s, int32_t b) {
     } else {
         slot = s->lru.back();  // least recently used
         s->lru.splice(s->lru.begin(), s->lru, s->where[slot]);
-        s->slot_of_block[s->block_of_slot[slot]] = -1;
+        if (s->block_of_slot[slot] >= 0) s->slot_of_block[s->block_of_slot[slot]] = -1;
         s->stats.evictions++;
     }
-    const int n = s->ncp[b], p = s->deg[b];
-    if (!read_at(s->fd, s->raw.data(), s->size[b], s->off[b])) return -1;
     s->stats.bytes_read += s->size[b];
     float *dst = s->slots + (int64_t)slot * s->slot_floats;
     const char *src = s->raw.data() + 1;
@@ -129,6 +153,19 @@ int32_t fetch_one(fa_store *s, int32_t b) {
     return slot;
 }
 
+fa_status fetch_status(int32_t code) {
+    return code == kFormatError ? FA_ERR_INVALID_ARG : FA_ERR_DEVICE;
+}
+
+// Wait for the gather of the previous fa_store_stage (it reads cache slots
+// that a refill would overwrite).
+bool wait_stage(fa_store *s) {
+    if (!s->stage_live) return true;
+    if (hipEventSynchronize(s->stage_ev) != hipSuccess) return false;
+    s->stage_live = false;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -140,12 +177,13 @@ fa_status fa_store_write(const char *path, int32_t nblocks, const fa_block *bloc
         const fa_block &B = blocks[b];
         const int n = B.ncp[0], p = B.degree[0];
         if (B.ncp[1] != n || B.ncp[2] != n || B.degree[1] != p || B.degree[2] != p || p < 1 ||
-            p > 255 || n < p + 1)
+            n < p + 1)
             return FA_ERR_INVALID_ARG;  // Eq. 2 stores one NCP and one degree per block
-        if (n > FA_MAX_NCP) return FA_ERR_UNSUPPORTED;
+        if (n > FA_MAX_NCP || p > FA_MAX_DEGREE) return FA_ERR_UNSUPPORTED;
         const float *t = knots + B.knot_off;
         for (int a = 0; a < 3; ++a)
-            if (t[a * (n + p + 1) + n + p] != 1.0f) return FA_ERR_INVALID_ARG;
+            if (t[a * (n + p + 1) + n + p] != 1.0f || !knots_ok(t + a * (n + p + 1), n, p))
+                return FA_ERR_INVALID_ARG;
     }
     FILE *f = fopen(path, "wb");
     if (!f) return FA_ERR_INVALID_ARG;
@@ -186,10 +224,15 @@ fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, 
         fa_store_close(s);
         return st;
     };
+    struct stat st;
+    if (fstat(fd, &st) != 0) return fail(FA_ERR_INVALID_ARG);
+    const int64_t fsize = (int64_t)st.st_size;
     if (!read_at(fd, magic, 4, 0) || std::memcmp(magic, kMagic, 4) != 0 ||
-        !read_at(fd, hdr, 12, 4) || hdr[0] != kVersion || hdr[1] <= 0)
+        !read_at(fd, hdr, 12, 4) || hdr[0] != kVersion || hdr[1] <= 0 ||
+        kHeader + (int64_t)hdr[1] * 16 > fsize)
         return fail(FA_ERR_INVALID_ARG);
     s->nblocks = hdr[1];
+    const int64_t first_record = kHeader + (int64_t)s->nblocks * 16;
     std::vector<int64_t> idx((size_t)s->nblocks * 2);
     if (!read_at(fd, idx.data(), (int64_t)idx.size() * 8, kHeader)) return fail(FA_ERR_INVALID_ARG);
     s->off.resize(s->nblocks);
@@ -200,10 +243,15 @@ fa_status fa_store_open(const char *path, int32_t cache_blocks, uint32_t flags, 
     for (int32_t b = 0; b < s->nblocks; ++b) {
         s->off[b] = idx[2 * b];
         s->size[b] = idx[2 * b + 1];
+        // every record lies inside the file, after the index
+        if (s->off[b] < first_record || s->size[b] < 1 || s->size[b] > fsize - s->off[b])
+            return fail(FA_ERR_INVALID_ARG);
         uint8_t p = 0;
-        if (s->size[b] < 1 || !read_at(fd, &p, 1, s->off[b])) return fail(FA_ERR_INVALID_ARG);
+        if (!read_at(fd, &p, 1, s->off[b])) return fail(FA_ERR_INVALID_ARG);
+        if (p < 1) return fail(FA_ERR_INVALID_ARG);
+        if (p > FA_MAX_DEGREE) return fail(FA_ERR_UNSUPPORTED);
         const int n = ncp_from_size(s->size[b], p);
-        if (p < 1 || n < 0) return fail(FA_ERR_INVALID_ARG);
+        if (n < 0) return fail(FA_ERR_INVALID_ARG);
         s->ncp[b] = n;
         s->deg[b] = p;
         s->slot_floats = std::max<int64_t>(s->slot_floats, knot_span(n, p) + (int64_t)n * n * n);
@@ -271,9 +319,11 @@ fa_status fa_store_fetch(fa_store *s, const int32_t *ids, int32_t n, int32_t *sl
     if (!s || (n > 0 && !ids) || n < 0) return FA_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i)
         if (ids[i] < 0 || ids[i] >= s->nblocks) return FA_ERR_INVALID_ARG;
+    // a gather of fa_store_stage may still read the slots this call refills
+    if (s->pinned && !wait_stage(s)) return FA_ERR_DEVICE;
     for (int32_t i = 0; i < n; ++i) {
         const int32_t slot = fetch_one(s, ids[i]);
-        if (slot < 0) return FA_ERR_DEVICE;
+        if (slot < 0) return fetch_status(slot);
         if (slots) slots[i] = slot;
     }
     if (stats) *stats = s->stats;
@@ -307,10 +357,8 @@ fa_status fa_store_stage(fa_store *s, const int32_t *ids, int32_t n, fa_block *d
     }
     if (kneed > knot_capacity || align64(cneed) > ctrl_capacity) return FA_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    if (s->stage_live) {  // the previous gather reads the table and its slots
-        if (hipEventSynchronize(s->stage_ev) != hipSuccess) return FA_ERR_DEVICE;
-        s->stage_live = false;
-    }
+    // the previous gather reads the table and its slots
+    if (!wait_stage(s)) return FA_ERR_DEVICE;
     int32_t batch = 0;
     auto flush = [&](bool wait) -> bool {
         if (batch == 0) return true;
@@ -328,7 +376,11 @@ fa_status fa_store_stage(fa_store *s, const int32_t *ids, int32_t n, fa_block *d
         // a batch as large as the cache could see its own slots refilled
         if (batch == s->capacity && !flush(true)) return FA_ERR_DEVICE;
         const int32_t slot = fetch_one(s, ids[i]);
-        if (slot < 0) return FA_ERR_DEVICE;
+        if (slot < 0) {
+            // entries already gathered into the table still go out
+            if (!flush(false)) return FA_ERR_DEVICE;
+            return fetch_status(slot);
+        }
         const int nn = s->ncp[ids[i]], p = s->deg[ids[i]];
         const int64_t kl = 3 * (nn + p + 1), cl = (int64_t)nn * nn * nn;
         co = align64(co);

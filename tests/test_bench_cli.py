@@ -23,16 +23,29 @@ def test_refuses_more_than_one_gpu():
                                              ("adjoint", "c4"), ("decode_mfma", "c5"),
                                              ("render", "f1"), ("fit", "f2")])
 def test_traffic_files_match_sources(kernel, workload):
-    """bench.py reports a committed traffic summary only when it was taken on
-    the kernel sources in the tree, and null otherwise."""
+    """Every committed traffic summary was taken on the kernel sources in the
+    tree (a kernel changed since its counters were read must be profiled
+    again), and bench.py reports its figure."""
     import bench
     with open(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")) as f:
         t = json.load(f)
-    if t["source_hash"] == bench.source_hash(kernel):
-        assert bench.traffic_from_profiles(kernel, workload) == t["hbm_bytes_per_launch"]
-    else:
-        assert bench.traffic_from_profiles(kernel, workload) is None
+    assert t["source_hash"] == bench.source_hash(kernel), \
+        f"profiles/{kernel}_{workload}_traffic.json is stale: profile the kernel again"
+    assert bench.traffic_from_profiles(kernel, workload) == t["hbm_bytes_per_launch"]
     # the counters see at least the algorithmic bytes (the render re-fetches
-    # lattice lines, about 4.7x; the others stay within 10%)
+    # lattice lines; the others stay within 10%)
     ratio = t["hbm_bytes_per_launch"] / t["alg_bytes_per_launch"]
     assert 0.99 < ratio < (5.0 if kernel == "render" else 1.2)
+
+
+def test_stale_traffic_summary_reports_null(tmp_path):
+    """A summary taken on other kernel sources is not reported."""
+    import bench
+    good = {"kernel": "decode_sep", "workload": "c2", "hbm_bytes_per_launch": 123.0,
+            "alg_bytes_per_launch": 120.0, "source_hash": bench.source_hash("decode_sep")}
+    (tmp_path / "decode_sep_c2_traffic.json").write_text(json.dumps(good))
+    assert bench.traffic_from_profiles("decode_sep", "c2", str(tmp_path)) == 123.0
+    stale = dict(good, source_hash="0" * 12)
+    (tmp_path / "decode_sep_c2_traffic.json").write_text(json.dumps(stale))
+    assert bench.traffic_from_profiles("decode_sep", "c2", str(tmp_path)) is None
+    assert bench.traffic_from_profiles("decode_sep", "c9", str(tmp_path)) is None

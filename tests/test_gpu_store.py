@@ -85,3 +85,34 @@ def test_stage_then_render_equals_resident_render(fa, tmp_path):
             assert st["bytes_h2d"] - prev["bytes_h2d"] > 0
         prev = st
     store.close()
+
+
+def test_fetch_after_stage_keeps_the_staged_batch(fa, tmp_path):
+    """A fetch right after a stage refills the cache slots the stage's gather
+    reads; it waits for that gather, so the staged batch holds the lattices
+    and knots of the staged blocks."""
+    say("stage then fetch")
+    nb = 3
+    b = _cubic_domain(26, nb)
+    full = fa.MicroModels.from_batch(b)
+    path = tmp_path / "dom.fam"
+    fa.store_write(path, full.host_desc, b.knots, b.ctrl)
+    store = fa.Store(path, cache_blocks=6, pinned=True)
+    ids = np.array([4, 0, 13, 7, 21, 2], np.int32)
+    staged, _ = store.stage(ids)
+    # every slot refilled with other blocks, no synchronisation in between
+    store.fetch(np.array([k for k in range(nb ** 3) if k not in set(ids)][:12], np.int32))
+    torch.cuda.synchronize()
+    desc = staged.desc.cpu().numpy().view(fa.BLOCK_DTYPE)[:ids.size]
+    kn = staged.knots.cpu().numpy()
+    P = staged.ctrl.cpu().numpy()
+    for i, k in enumerate(ids):
+        n, p = int(b.ncp[k, 0]), int(b.deg[k, 0])
+        d = desc[i]
+        assert int(d["ncp"][0]) == n
+        assert np.array_equal(P[d["ctrl_off"]:d["ctrl_off"] + n ** 3],
+                              b.ctrl[b.ctrl_off[k]:b.ctrl_off[k] + n ** 3])
+        kl = 3 * (n + p + 1)
+        assert np.array_equal(kn[d["knot_off"]:d["knot_off"] + kl],
+                              b.knots[b.knot_off[k]:b.knot_off[k] + kl])
+    store.close()

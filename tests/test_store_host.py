@@ -114,3 +114,84 @@ def test_store_rejects_bad_input(fa, tmp_path):
     assert fa.lib.fa_store_stage(s.h, ids.ctypes.data, 1, vp, vp, 1 << 20, vp, 1 << 20, None,
                                  None) == 1
     s.close()
+
+
+def test_truncated_file_is_refused_at_open(fa, tmp_path):
+    """A record that reaches past the end of the file is refused by
+    fa_store_open (before any fetch can read it into the cache)."""
+    b, desc = _batch(fa, 84, 6)
+    path = tmp_path / "m.fam"
+    fa.store_write(path, desc, b.knots, b.ctrl)
+    raw = path.read_bytes()
+    (tmp_path / "cut.fam").write_bytes(raw[:-7])
+    with pytest.raises(fa.FAError) as e:
+        fa.Store(tmp_path / "cut.fam", pinned=False)
+    assert e.value.status == fa.FA_ERR_INVALID_ARG
+    # an index entry pointing into the header is refused as well
+    bad = bytearray(raw)
+    bad[16:24] = struct.pack("<q", 4)
+    (tmp_path / "hdr.fam").write_bytes(bytes(bad))
+    with pytest.raises(fa.FAError):
+        fa.Store(tmp_path / "hdr.fam", pinned=False)
+
+
+def test_failed_fetch_leaves_cache_unchanged(fa, tmp_path):
+    """A record with malformed knots fails its fetch without touching the
+    LRU: later fetches (with evictions) behave as if it was never asked for."""
+    b, desc = _batch(fa, 85, 8)
+    path = tmp_path / "m.fam"
+    fa.store_write(path, desc, b.knots, b.ctrl)
+    raw = bytearray(path.read_bytes())
+    idx = np.frombuffer(bytes(raw[16:16 + 16 * 8]), np.int64).reshape(8, 2)
+    bad_id = 5
+    off = int(idx[bad_id, 0])
+    # first x knot of block 5 set to 0.5: no longer clamped at 0
+    raw[off + 1:off + 5] = struct.pack("<f", 0.5)
+    (tmp_path / "k.fam").write_bytes(bytes(raw))
+    s = fa.Store(tmp_path / "k.fam", cache_blocks=2, pinned=False)
+    s.fetch([0])
+    with pytest.raises(fa.FAError) as e:
+        s.fetch([bad_id])
+    assert e.value.status == fa.FA_ERR_INVALID_ARG
+    # the failed fetch counted nothing and took no slot: 0 is still cached
+    slots, st = s.fetch([0, 1, 2, 3])
+    assert (st["hits"], st["misses"], st["evictions"]) == (1, 4, 2)
+    for k, sl in zip([2, 3], slots[2:]):
+        blk, kn, P = s.slot(sl)
+        n = int(b.ncp[k, 0])
+        assert blk == k
+        assert np.array_equal(P.reshape(-1), b.ctrl[b.ctrl_off[k]:b.ctrl_off[k] + n ** 3])
+    s.close()
+
+
+def test_degree_above_kernel_limit_is_unsupported(fa, tmp_path):
+    """Degrees the kernels do not take are refused when written and when a
+    file holding one is opened."""
+    n, p = 6, 4
+    kn = np.concatenate([np.zeros(p + 1), np.arange(1, n - p) / (n - p), np.ones(p + 1)])
+    knots = np.tile(kn.astype(np.float32), 3)
+    ctrl = np.zeros(n ** 3, np.float32)
+    desc = np.zeros(1, fa.BLOCK_DTYPE)
+    desc["ncp"][0] = n
+    desc["degree"][0] = p
+    with pytest.raises(fa.FAError) as e:
+        fa.store_write(tmp_path / "p4.fam", desc, knots, ctrl)
+    assert e.value.status == fa.FA_ERR_UNSUPPORTED
+    # the same record written by hand (Eq. 2 bytes) is refused at open
+    rec = bytes([p]) + b"".join(kn[:-1].astype(np.float32).tobytes() for _ in range(3)) + \
+        ctrl.tobytes()
+    head = b"FAM1" + struct.pack("<iii", 1, 1, 0) + struct.pack("<qq", 32, len(rec))
+    (tmp_path / "p4h.fam").write_bytes(head + rec)
+    with pytest.raises(fa.FAError) as e:
+        fa.Store(tmp_path / "p4h.fam", pinned=False)
+    assert e.value.status == fa.FA_ERR_UNSUPPORTED
+
+
+def test_write_refuses_unclamped_or_decreasing_knots(fa, tmp_path):
+    b, desc = _batch(fa, 86, 2, degs=(3,), ncps=(9,))
+    for pos, val in ((1, 0.25), (6, 0.1)):  # a leading zero moved; a decreasing interior knot
+        kn = b.knots.copy()
+        kn[b.knot_off[1] + pos] = val
+        with pytest.raises(fa.FAError) as e:
+            fa.store_write(tmp_path / "bad.fam", desc, kn, b.ctrl)
+        assert e.value.status == fa.FA_ERR_INVALID_ARG
