@@ -394,6 +394,33 @@ fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const floa
                              double *sumsq, void *workspace, int64_t workspace_bytes,
                              void *stream);
 
+/*
+ * fa_decode_residual for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results (bit for bit), with
+ * the per-item FP64 partial sums kept in a fixed device array of the
+ * library, FA_NOALLOC_SCRATCH_BYTES long, instead of a caller workspace.
+ * The call allocates nothing (no hipMalloc, no allocating library call);
+ * the caller still passes the outputs.  The first call on a device looks up
+ * that device's array (hipGetSymbolAddress); make it outside a graph
+ * capture.  Every call on one GPU shares that GPU's array and leaves the
+ * last call's partial sums in it (each call writes every partial it reads,
+ * so nothing needs clearing): calls that overlap on one GPU, on different
+ * streams or from different threads, race and must be serialised by the
+ * caller.  FA_ERR_UNSUPPORTED when fa_decode_residual_workspace(nblocks,
+ * res, tune) exceeds FA_NOALLOC_SCRATCH_BYTES (more than 131072 work items,
+ * e.g. more than 16384 blocks at 64^3 with 8 y rows per item); otherwise
+ * errors as fa_decode_residual, FA_ERR_DEVICE if the array's address cannot
+ * be resolved.
+ */
+#define FA_NOALLOC_SCRATCH_BYTES (1 << 20)
+fa_status fa_decode_residual_noalloc(const fa_block *blocks, int32_t nblocks,
+                                     const float *knots, const float *ctrl,
+                                     const int32_t res[3], const fa_tune *tune,
+                                     const fa_work *work, const int32_t *wg_off,
+                                     int32_t ngroups, const float *samples, float grad_scale,
+                                     float *grad, double *sumsq, void *stream);
+
 /* Bytes of device workspace fa_ncp_search needs (-1 for invalid sizes). */
 int64_t fa_ncp_search_workspace(int32_t nblocks, const int32_t res[3], int32_t degree,
                                 int32_t ncp_hi);

@@ -29,6 +29,7 @@ _LIB_PATH = os.environ.get("FA_LIBRARY") or os.path.join(_HERE, "libfa.so")
 
 FA_OK, FA_ERR_INVALID_ARG, FA_ERR_UNSUPPORTED, FA_ERR_DEVICE = 0, 1, 2, 3
 FA_F32, FA_BF16, FA_F16 = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 1 << 20  # FA_NOALLOC_SCRATCH_BYTES
 DTYPES = {"f32": FA_F32, "bf16": FA_BF16, "f16": FA_F16}
 
 BLOCK_DTYPE = np.dtype([("ncp", "<i4", (3,)), ("degree", "<i4", (3,)), ("knot_off", "<i8"),
@@ -108,6 +109,9 @@ def _load():
     L.fa_decode_residual.restype = ctypes.c_int
     L.fa_decode_residual.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, ctypes.c_float,
                                      vp, vp, vp, i64, vp]
+    L.fa_decode_residual_noalloc.restype = ctypes.c_int
+    L.fa_decode_residual_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
+                                             ctypes.c_float, vp, vp, vp]
     L.fa_fit_workspace.restype = i64
     L.fa_fit_workspace.argtypes = [i32, vp, i32]
     L.fa_fit_blocks.restype = ctypes.c_int
@@ -660,6 +664,33 @@ def decode_residual(models, res, samples, grad_scale, plan=None, tune=None, grad
                                 _ptr(samples), float(grad_scale), _ptr(grad), _ptr(sumsq),
                                 _ptr(workspace), int(workspace.numel()), _stream(stream))
     _check("fa_decode_residual", st)
+    return grad, sumsq
+
+
+def decode_residual_noalloc(models, res, samples, grad_scale, plan=None, tune=None, grad=None,
+                            sumsq=None, stream=None):
+    """decode_residual through fa_decode_residual_noalloc: the partial sums
+    live in the library's fixed device array, so the call itself allocates
+    nothing (pass grad and sumsq to keep this wrapper from allocating them).
+    Calls that overlap on one GPU race on that array."""
+    res3 = _i32x3(res)
+    if plan is not None:
+        assert plan.res == tuple(int(r) for r in res)
+        t, work, off, ng = plan.tune, _ptr(plan.work), _ptr(plan.wg_off), plan.ngroups
+    else:
+        t = tune if tune is not None else FATune(0, 0, 0, 0, 0, 0)
+        work, off, ng = None, None, 0
+    if grad is None:
+        grad = torch.empty((models.nblocks,) + tuple(int(r) for r in res), dtype=torch.float32,
+                           device=models.device)
+    if sumsq is None:
+        sumsq = torch.empty(models.nblocks, dtype=torch.float64, device=models.device)
+    assert samples.dtype == torch.float32 and samples.is_contiguous()
+    st = lib.fa_decode_residual_noalloc(_ptr(models.desc), models.nblocks, _ptr(models.knots),
+                                        _ptr(models.ctrl), res3, ctypes.byref(t), work, off, ng,
+                                        _ptr(samples), float(grad_scale), _ptr(grad),
+                                        _ptr(sumsq), _stream(stream))
+    _check("fa_decode_residual_noalloc", st)
     return grad, sumsq
 
 

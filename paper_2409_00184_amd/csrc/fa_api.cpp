@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <vector>
@@ -15,6 +16,9 @@
 #include "fa_internal.hpp"
 
 using namespace fa;
+
+// Scratch of fa_decode_residual_noalloc (see scratch_address below).
+static __device__ __align__(256) double scratch[FA_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
 namespace {
 
@@ -107,6 +111,74 @@ int64_t items_per_block(const int32_t res[3], const Tune &t) {
     return (int64_t)((res[1] + t.rows - 1) / t.rows) * ((res[2] + kWaveLanes - 1) / kWaveLanes);
 }
 
+
+// `scratch` holds the per-item FP64 partial sums of
+// fa_decode_residual_noalloc in a device array of fixed size (each GPU the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes `scratch` itself to a kernel (in host code the name stands
+// for a host-side placeholder, not the device array); it uses the device
+// address that hipGetSymbolAddress returns, resolved once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_of[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+hipError_t scratch_address(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_of[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_of[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_of[dev];
+    return hipSuccess;
+}
+
+// fa_decode_residual with its per-item partial sums in `partials`
+// (partials_bytes long), or, with partials null, in the current device's
+// scratch array (fa_decode_residual_noalloc).  Every argument check comes
+// before the scratch lookup and any launch.
+fa_status decode_residual_impl(const fa_block *blocks, int32_t nblocks, const float *knots,
+                               const float *ctrl, const int32_t res[3], const fa_tune *tune,
+                               const fa_work *work, const int32_t *wg_off, int32_t ngroups,
+                               const float *samples, float grad_scale, float *grad,
+                               double *sumsq, int64_t partials_bytes, double *partials,
+                               void *stream) {
+    if (!blocks || !knots || !ctrl || !samples || !grad || !sumsq || nblocks <= 0 ||
+        !res_ok(res) || !std::isfinite(grad_scale))
+        return FA_ERR_INVALID_ARG;
+    if ((work == nullptr) != (wg_off == nullptr)) return FA_ERR_INVALID_ARG;
+    if (work && ngroups <= 0) return FA_ERR_INVALID_ARG;
+    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
+    Tune t = resolve(tune);
+    if (!tune || tune->waves <= 0) t.waves = kReduceWaves;
+    if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
+    if (t.kernel != 0) return FA_ERR_UNSUPPORTED;
+    const int64_t need = (int64_t)nblocks * items_per_block(res, t) * (int64_t)sizeof(double);
+    if (partials) {
+        if (partials_bytes < need) return FA_ERR_INVALID_ARG;
+    } else {
+        if (need > FA_NOALLOC_SCRATCH_BYTES) return FA_ERR_UNSUPPORTED;
+        if (scratch_address(&partials) != hipSuccess) return FA_ERR_DEVICE;
+    }
+    DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, FA_F32, res, 1u, t, work, wg_off,
+                               grad);
+    a.samples = samples;
+    a.gscale = grad_scale;
+    a.partials = partials;
+    const int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
+    hipError_t e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_residual_combine(a.partials, nblocks, a.nrowt * a.ncolt, sumsq,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
 
 }  // namespace
 
@@ -280,29 +352,20 @@ fa_status fa_decode_residual(const fa_block *blocks, int32_t nblocks, const floa
                              const float *samples, float grad_scale, float *grad,
                              double *sumsq, void *workspace, int64_t workspace_bytes,
                              void *stream) {
-    if (!blocks || !knots || !ctrl || !samples || !grad || !sumsq || !workspace ||
-        nblocks <= 0 || !res_ok(res) || !std::isfinite(grad_scale))
-        return FA_ERR_INVALID_ARG;
-    if ((work == nullptr) != (wg_off == nullptr)) return FA_ERR_INVALID_ARG;
-    if (work && ngroups <= 0) return FA_ERR_INVALID_ARG;
-    if (!res_supported(res)) return FA_ERR_UNSUPPORTED;
-    Tune t = resolve(tune);
-    if (!tune || tune->waves <= 0) t.waves = kReduceWaves;
-    if (!tune_ok(t)) return FA_ERR_INVALID_ARG;
-    if (t.kernel != 0) return FA_ERR_UNSUPPORTED;
-    const int64_t need = fa_decode_residual_workspace(nblocks, res, tune);
-    if (need < 0 || workspace_bytes < need) return FA_ERR_INVALID_ARG;
-    DecodeLaunch a = grid_args(blocks, nblocks, knots, ctrl, FA_F32, res, 1u, t, work, wg_off,
-                               grad);
-    a.samples = samples;
-    a.gscale = grad_scale;
-    a.partials = static_cast<double *>(workspace);
-    const int grid = work ? ngroups : (int)std::min<int64_t>(a.nitems, default_grid(t, a.nitems));
-    hipError_t e = launch_decode_sep(a, t.waves, grid, (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = launch_residual_combine(a.partials, nblocks, a.nrowt * a.ncolt, sumsq,
-                                    (hipStream_t)stream);
-    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+    if (!workspace) return FA_ERR_INVALID_ARG;
+    return decode_residual_impl(blocks, nblocks, knots, ctrl, res, tune, work, wg_off, ngroups,
+                                samples, grad_scale, grad, sumsq, workspace_bytes,
+                                static_cast<double *>(workspace), stream);
+}
+
+fa_status fa_decode_residual_noalloc(const fa_block *blocks, int32_t nblocks,
+                                     const float *knots, const float *ctrl,
+                                     const int32_t res[3], const fa_tune *tune,
+                                     const fa_work *work, const int32_t *wg_off,
+                                     int32_t ngroups, const float *samples, float grad_scale,
+                                     float *grad, double *sumsq, void *stream) {
+    return decode_residual_impl(blocks, nblocks, knots, ctrl, res, tune, work, wg_off, ngroups,
+                                samples, grad_scale, grad, sumsq, 0, nullptr, stream);
 }
 
 fa_status fa_decode_blocks_plain(const fa_block *blocks, int32_t nblocks, const float *knots,

@@ -220,6 +220,14 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, 0, None) == 2
     assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
+    # the allocation-free residual: bad arguments, then a batch whose work
+    # items exceed its fixed scratch array, both before any device call
+    assert L.fa_decode_residual_noalloc(None, 1, vp, vp, r, None, None, None, 0, vp, 1.0, vp,
+                                        vp, None) == 1
+    assert L.fa_decode_residual_noalloc(vp, 1, vp, vp, r, None, None, None, 0, vp,
+                                        float("inf"), vp, vp, None) == 1
+    assert L.fa_decode_residual_noalloc(vp, 20000, vp, vp, r, None, None, None, 0, vp, 1.0, vp,
+                                        vp, None) == 2
     assert L.fa_decode_blocks_plain(vp, 1, vp, None, r, 15, vp, None) == 1
 
 
