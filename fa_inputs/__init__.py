@@ -328,6 +328,24 @@ def config_c5(seed=5, nblocks=4096, n=32, p=3):
     return out
 
 
+def voxel_subset(nblocks, res, frac=0.01, seed=55):
+    """A seeded uniform sample, without replacement, of floor(frac * N) of the
+    N = nblocks * res0 * res1 * res2 (block, voxel) pairs of a grid decode,
+    as int32 [k, 4] rows (block, x, y, z) in increasing flat order.  At C5
+    (4096 blocks of 64^3) the 1% sample holds 10,737,418 pairs."""
+    res = tuple(int(r) for r in res)
+    vox = res[0] * res[1] * res[2]
+    total = int(nblocks) * vox
+    flat = np.sort(rng(seed).choice(total, size=int(total * frac), replace=False))
+    out = np.empty((flat.size, 4), np.int32)
+    out[:, 0] = flat // vox
+    r = flat % vox
+    out[:, 1] = r // (res[1] * res[2])
+    out[:, 2] = (r // res[2]) % res[1]
+    out[:, 3] = r % res[2]
+    return out
+
+
 # ----------------------------------------------------------- Marschner-Lobb
 
 ML_FM, ML_ALPHA, ML_EXTENT = 6.0, 0.05, 7.0

@@ -16,6 +16,8 @@ paper cites in Sec. 1 -- and the micro-model content of Sec. 4.2 / Eq. 2):
   corners     clamped knots interpolate the corner control points, and the
               end derivative is p/(t_{p+1}) (P_1 - P_0)
   fd          central differences of the value match the gradient
+  one_sided   at a knot of multiplicity p the derivative is the one from
+              the right; at a double knot of a cubic both sides agree
   brute       local evaluation equals the all-basis brute force
   adjoint     <B P, g> = <P, B^T g>
   query       block lookup + chain rule on a tiled domain of linear blocks
@@ -248,6 +250,44 @@ def pin_fd():
             assert np.abs(fd - out[:, 1 + a]).max() < 1e-5 * scale, (a, np.abs(fd - out[:, 1 + a]).max())
 
 
+def pin_one_sided():
+    """At an interior knot of multiplicity m the spline is C^{p-m}.  At a
+    knot of multiplicity p the derivative jumps, and the right-continuous
+    span rule makes the value at the knot the derivative from the right: it
+    equals a second-order one-sided difference from the right and not the
+    one from the left.  At a double knot of a cubic (C^1) both one-sided
+    differences give it."""
+    g = fi.rng(113)
+    h = 1e-5
+
+    def right(f, t):
+        return (-3 * f(t) + 4 * f(t + h) - f(t + 2 * h)) / (2 * h)
+
+    def left(f, t):
+        return (3 * f(t) - 4 * f(t - h) + f(t - 2 * h)) / (2 * h)
+
+    for p, mult, jumps in ((2, 2, True), (3, 3, True), (3, 2, False), (1, 1, True)):
+        n = p + 1 + mult + 2
+        k = 0.375  # exact in FP32 and FP64
+        inner = np.sort(np.concatenate([[0.125], [k] * mult, [0.8125]]))
+        assert len(inner) == n - p - 1
+        t = np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+        P = g.normal(size=(n, 2, 2))
+        blk = single([n, 2, 2], [p, 1, 1], [t, [0, 0, 1, 1], [0, 0, 1, 1]], P)
+
+        def f(u):
+            return oracle.eval_params(blk, [0], [[u, 0.3, 0.6]])[0, 0]
+
+        d = oracle.eval_params(blk, [0], [[k, 0.3, 0.6]])[0, 1]
+        dr, dl = right(f, k), left(f, k)
+        scale = 1.0 + abs(dr) + abs(dl)
+        assert abs(d - dr) < 1e-6 * scale, (p, mult, d, dr)
+        if jumps:
+            assert abs(dl - dr) > 1e-3 * scale, (p, mult, dl, dr)
+        else:
+            assert abs(d - dl) < 1e-6 * scale, (p, mult, d, dl)
+
+
 def pin_brute():
     g = fi.rng(108)
     for trial in range(12):
@@ -417,5 +457,5 @@ def pin_render():
 
 
 ALL_PINS = [pin_span, pin_unity, pin_bernstein, pin_cardinal, pin_linear, pin_quadratic,
-            pin_corners, pin_fd, pin_brute, pin_decode_layout, pin_adjoint, pin_query,
+            pin_corners, pin_fd, pin_one_sided, pin_brute, pin_decode_layout, pin_adjoint, pin_query,
             pin_render]

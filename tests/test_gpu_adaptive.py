@@ -11,33 +11,65 @@ from oracle import adaptive as ad
 
 pytestmark = pytest.mark.gpu
 
-# Tolerances of the fit.  The GPU builds each per-axis pseudo-inverse in FP64
-# from an FP64 basis at the same FP32 grid positions and knots as the
-# oracle, contracts in FP64 and rounds the lattice to FP32 once, so
-#   |P_gpu - P| <= u32 |P| + c64 max|P|,  c64 = 1e3 u64 sum_a kappa(B_a)^2
-# (FP64 rounding amplified by the per-axis Gram matrices' condition numbers;
-# kappa(B_a) from the oracle's FP64 collocation matrices).  The error map
-# entries move by at most the decoded model's change, |f_gpu - f|_inf <=
-# |P_gpu - P|_inf (rows of B are convex weights) plus the FP32 decode's own
-# rounding (64 u32 max |P|):  tol = (80 u32 + c64) max |P|.  max |P| grows
-# when NCP approaches R on the uniform grid (kappa(B_a) about 4e4 at
+# Tolerance of the fit (a first-order error estimate, derived step by step
+# in the design doc's conditioning paragraph).  Per axis a the GPU solves
+# G_a X_a = B_a^T in FP64 (G_a = B_a^T B_a formed in FP64, band Cholesky of
+# half-bandwidth p, two band triangular solves) and applies the three X_a to
+# the samples as FP64 contractions of length R_a; the lattice is rounded to
+# FP32 once.  The solve is backward stable with a perturbation of G_a of
+# relative size
+#   eps_a = gamma(R_a)                  Gram sums (B >= 0: no cancellation)
+#         + (2p+1) gamma(3(p+1)+1)      band Cholesky and solves; the
+#                                       factor bounds || |R^T||R| || / ||G||
+#         + 4 gamma(5p)                 FP64 basis of the GPU and of the
+#                                       oracle (5 roundings per recursion
+#                                       level, non-negative terms)
+# which moves the solution by kappa(G_a) eps_a = kappa(B_a)^2 eps_a
+# relative to max |P|; the oracle's library solve moves it by at most as
+# much (factor 2), and the three contractions add gamma(R_x + R_y + R_z):
+#   |P_gpu - P| <= u32 |P| + (2 sum_a kappa(B_a)^2 eps_a + gamma(3R)) max|P|.
+# The error map entries move by at most the decoded model's change,
+# |f_gpu - f|_inf <= |P_gpu - P|_inf (rows of B are convex weights), plus the
+# FP32 decode's own rounding (64 u32 max |P|): c32 = 80 covers both FP32
+# terms there.  kappa(B_a) grows quickly as NCP approaches R (about 4e4 at
 # NCP = R = 64 for cubics), and with it the error any FP32 model can have.
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
 
 
-def svals(ncp, deg, R):
-    """(product of smallest singular values, sum of kappa(B_a)^2)."""
-    lo, k2 = 1.0, 0.0
+def gamma(k):
+    return k * U64 / (1.0 - k * U64)
+
+
+def kappas2(ncp, deg, R):
+    """kappa(B_a)^2 of the oracle's FP64 collocation matrices, per axis."""
+    out = []
     for a in range(3):
         B = ad.collocation(ncp[a], deg[a], ad.uniform_knots(ncp[a], deg[a]), R[a])
         sv = np.linalg.svd(B, compute_uv=False)
-        lo, k2 = lo * sv[-1], k2 + (sv[0] / sv[-1]) ** 2
-    return lo, k2
+        out.append((sv[0] / sv[-1]) ** 2)
+    return out
+
+
+def svals(ncp, deg, R):
+    """Product of the axes' smallest singular values."""
+    lo = 1.0
+    for a in range(3):
+        B = ad.collocation(ncp[a], deg[a], ad.uniform_knots(ncp[a], deg[a]), R[a])
+        lo *= np.linalg.svd(B, compute_uv=False)[-1]
+    return lo
+
+
+def fit_rel(ncp, deg, R):
+    """Multiplier of max |P| in the fit's error estimate (FP64 part)."""
+    k2 = kappas2(ncp, deg, R)
+    eps = [gamma(R[a]) + (2 * deg[a] + 1) * gamma(3 * (deg[a] + 1) + 1) + 4 * gamma(5 * deg[a])
+           for a in range(3)]
+    return 2.0 * sum(k * e for k, e in zip(k2, eps)) + gamma(sum(R))
 
 
 def tol_from(P, ncp, deg, R, c32=80.0):
-    return (c32 * U32 + 1e3 * U64 * svals(ncp, deg, R)[1]) * np.abs(P).max()
+    return (c32 * U32 + fit_rel(ncp, deg, R)) * np.abs(P).max()
 
 
 @pytest.fixture(scope="module")
@@ -121,7 +153,7 @@ def test_fit_recovers_spline(fa):
         dg, RR = (degs[b],) * 3, (R,) * 3
         # y is the FP32 rounding of the exact decode of P, so P is the exact
         # fit of data within u32 |y|_2 of y: |P - fit(y)|_2 <= u32 |y|_2 / s_min
-        lo, _ = svals(ncp[b], dg, RR)
+        lo = svals(ncp[b], dg, RR)
         tol = U32 * np.linalg.norm(Y[b]) / lo + tol_from(P[o:o + n], ncp[b], dg, RR, c32=1.0)
         d = np.abs(got[o:o + n] - P[o:o + n]).max()
         say("  block", b, ncp[b], "err", d, "tol", tol)

@@ -47,3 +47,16 @@ def test_rays_hit_cube():
     assert np.all(xyz > -1e-5) and np.all(xyz < 1 + 1e-5)
     o, d, t0, t1, j = fi.camera_rays(3, 32, 18)
     assert np.all(t1 > t0)
+
+
+def test_voxel_subset_is_a_seeded_sample_without_replacement():
+    s = fi.voxel_subset(7, (5, 6, 9), frac=0.1, seed=3)
+    total = 7 * 5 * 6 * 9
+    assert s.shape == (int(total * 0.1), 4) and s.dtype == np.int32
+    flat = ((s[:, 0] * 5 + s[:, 1]) * 6 + s[:, 2]) * 9 + s[:, 3]
+    assert np.all(np.diff(flat) > 0)  # distinct, increasing
+    assert s[:, 0].max() < 7 and s[:, 1].max() < 5 and s[:, 2].max() < 6 and s[:, 3].max() < 9
+    assert s.min() >= 0
+    assert np.array_equal(s, fi.voxel_subset(7, (5, 6, 9), frac=0.1, seed=3))
+    # 1% of C5's 4096 x 64^3 pairs
+    assert int(4096 * 64 ** 3 * 0.01) == 10_737_418
