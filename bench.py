@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Throughput of the micro-model decode/query path on one MI355X.
 
-Default workload (C2): batched decode of 512 micro-models with NCP* per axis
+Headline workload (C2): batched decode of 512 micro-models with NCP* per axis
 drawn from {8,12,16,24,32} and degree from {2,3}, each decoded to a 64^3
-voxel grid (value + 3 gradient channels, FP32), as one persistent launch
-replayed from a captured HIP graph, schedule picked by the autotuner.
+voxel grid (value + 3 gradient channels, FP32), as one launch replayed from a
+captured HIP graph, schedule picked by the autotuner.  The default run
+prints the C2 line with the ray-sample query (C3), the fit iteration (C4)
+and the BF16/FP16 precision configuration (C5) as sub-records.
 
 One step = one decode of the whole batch with inputs resident in HBM.
 Prints one JSON line (rank 0) with the throughput, the roofline of the
@@ -98,30 +100,61 @@ def timed_steps(fn, steps, warmup, stream):
     return wall * 1e3 / steps, sum(ev_ms) / len(ev_ms), min(ev_ms)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(run, kmax, target_s, unit, scale, what):
+    """Time the FP64 oracle as it stands: run(k, threads) evaluates the
+    first k units of a seeded order.  Calibrated on one unit, then sized for
+    about target_s on every host thread the oracle uses, and for a quarter of
+    that on one thread; value = units * scale / s."""
+    import oracle
+    th = oracle.nthreads_default()
+    t0 = time.perf_counter()
+    run(1, th)
+    t1 = max(time.perf_counter() - t0, 1e-4)
+    k = int(max(1, min(kmax, target_s / t1)))
+    t0 = time.perf_counter()
+    run(k, th)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run(1, 1)
+    s1 = max(time.perf_counter() - t0, 1e-4)
+    k1 = int(max(1, min(kmax, 0.25 * target_s / s1)))
+    t0 = time.perf_counter()
+    run(k1, 1)
+    d1 = time.perf_counter() - t0
+    return {"value": k * scale / dt, "unit": unit, "cores": th, "kind": "oracle",
+            "sample": f"{k} {what}, {dt:.1f} s", "cpu_model": cpu_model(),
+            "single_core": {"value": k1 * scale / d1, "sample": f"{k1} {what}, {d1:.1f} s"}}
+
+
 def cpu_baseline_decode(batch, res, target_s=15.0):
     """The FP64 oracle (as it stands) on a seeded sample of whole blocks."""
     import numpy as np
 
     import oracle
-    th = oracle.nthreads_default()
     ob = oracle.Blocks(batch.ncp, batch.deg, batch.knot_off, batch.ctrl_off, batch.knots,
                        batch.ctrl)
-    g = np.random.Generator(np.random.PCG64(99))
-    order = g.permutation(batch.nblocks)
-    vox = int(np.prod(res))
-    # calibrate on one block, then size the sample for ~target_s
-    sub = lambda k: oracle.Blocks(ob.ncp[order[:k]], ob.deg[order[:k]], ob.knot_off[order[:k]],
-                                  ob.ctrl_off[order[:k]], ob.knots, ob.ctrl)
-    t0 = time.perf_counter()
-    oracle.decode_blocks(sub(1), res, 15, nthreads=th)
-    t1 = time.perf_counter() - t0
-    k = int(max(1, min(batch.nblocks, target_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.decode_blocks(sub(k), res, 15, nthreads=th)
-    dt = time.perf_counter() - t0
-    return {"value": k * vox / dt, "unit": "voxels/s", "cores": th, "kind": "oracle",
-            "sample": f"{k} of {batch.nblocks} blocks (seeded), full {res[0]}^3 grids, "
-                      f"value+grad, FP64, {dt:.1f} s"}
+    order = np.random.Generator(np.random.PCG64(99)).permutation(batch.nblocks)
+
+    def run(k, th):
+        sel = order[:k]
+        oracle.decode_blocks(oracle.Blocks(ob.ncp[sel], ob.deg[sel], ob.knot_off[sel],
+                                           ob.ctrl_off[sel], ob.knots, ob.ctrl), res, 15,
+                             nthreads=th)
+
+    return oracle_rate(run, batch.nblocks, target_s, "voxels/s", int(np.prod(res)),
+                       f"of {batch.nblocks} blocks (seeded), full {res[0]}x{res[1]}x{res[2]} "
+                       "grids, value+grad, FP64")
 
 
 def cpu_baseline_fit(batch, y, res, target_s=15.0):
@@ -130,31 +163,21 @@ def cpu_baseline_fit(batch, y, res, target_s=15.0):
     import numpy as np
 
     import oracle
-    th = oracle.nthreads_default()
-    g = np.random.Generator(np.random.PCG64(98))
-    order = g.permutation(batch.nblocks)
+    order = np.random.Generator(np.random.PCG64(98)).permutation(batch.nblocks)
     ob = oracle.Blocks(batch.ncp, batch.deg, batch.knot_off, batch.ctrl_off, batch.knots,
                        batch.ctrl)
+    y64 = np.asarray(y, np.float64).reshape(batch.nblocks, 1, *res)
 
-    def run(k):
+    def run(k, th):
         sel = order[:k]
         sub = oracle.Blocks(ob.ncp[sel], ob.deg[sel], ob.knot_off[sel], ob.ctrl_off[sel],
                             ob.knots, ob.ctrl)
         f = oracle.decode_blocks(sub, res, 1, nthreads=th)
-        r = f - np.asarray(y, np.float64).reshape(batch.nblocks, 1, *res)[sel]
-        oracle.decode_adjoint(sub, res, r, 1, nthreads=th)
+        oracle.decode_adjoint(sub, res, f - y64[sel], 1, nthreads=th)
 
-    t0 = time.perf_counter()
-    run(1)
-    t1 = time.perf_counter() - t0
-    k = int(max(1, min(batch.nblocks, target_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    run(k)
-    dt = time.perf_counter() - t0
-    return {"value": k / batch.nblocks / dt, "unit": "iterations/s", "cores": th,
-            "kind": "oracle",
-            "sample": f"{k} of {batch.nblocks} blocks (seeded): FP64 value decode, residual and "
-                      f"adjoint, {dt:.1f} s, scaled to the whole batch (optimizer step excluded)"}
+    return oracle_rate(run, batch.nblocks, target_s, "iterations/s", 1.0 / batch.nblocks,
+                       f"of {batch.nblocks} blocks (seeded): FP64 value decode, residual and "
+                       "adjoint, scaled to the whole batch (optimizer step excluded)")
 
 
 def err_vs_oracle_decode(batch, out, res, nsample=20000, src=None, interleaved=False):
@@ -410,22 +433,16 @@ def bench_c3(args):
                                       for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}}
         line["lowp"] = lp
     if not args.no_cpu_baseline:
-        th = oracle.nthreads_default()
-        t0 = time.perf_counter()
-        oracle.query_points(ob, xs[:20000], (16, 16, 16), (0, 0, 0), (1, 1, 1),
-                            fi.identity_cells(4096), nthreads=th)
-        rate = 20000 / (time.perf_counter() - t0)
-        k = int(min(2e7, max(20000, rate * args.cpu_seconds)))
-        idx2 = torch.as_tensor(g.integers(0, n, k), device="cuda")
-        xk = xyz[idx2].cpu().numpy()
-        del idx2
-        t0 = time.perf_counter()
-        oracle.query_points(ob, xk, (16, 16, 16), (0, 0, 0), (1, 1, 1),
-                            fi.identity_cells(4096), nthreads=th)
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": k / dt, "unit": "samples/s", "cores": th,
-                                "kind": "oracle",
-                                "sample": f"{k} seeded samples of the 1.06e9, FP64, {dt:.1f} s"}
+        k_max = 20_000_000
+        sidx = torch.as_tensor(g.integers(0, n, k_max), device="cuda")
+        xk = xyz[sidx].cpu().numpy()
+        del sidx
+        cells = fi.identity_cells(4096)
+        line["cpu_baseline"] = oracle_rate(
+            lambda k, th: oracle.query_points(ob, xk[:20000 * k], (16, 16, 16), (0, 0, 0),
+                                              (1, 1, 1), cells, nthreads=th),
+            k_max // 20000, args.cpu_seconds, "samples/s", 20000,
+            "x 20000 seeded samples of the 1.06e9 (ray-major positions), FP64")
     del xyz, out
     return line
 
@@ -841,7 +858,7 @@ def bench_c4(args):
 
     stream = torch.cuda.current_stream()
     ms, ev_ms, _ = timed_steps(lambda: losses.append(it()), args.steps, args.warmup, stream)
-    first, last = float(losses[0]), float(losses[-1])
+    first, last = float(losses[0].detach()), float(losses[-1].detach())
     ms_t = timed_steps(it_torch, args.steps, args.warmup, stream)[0]
     # the same iteration captured into one HIP graph (the same fused Adam,
     # capturable); every replay does the whole iteration's work
@@ -860,6 +877,29 @@ def bench_c4(args):
                               stream)
     nvox = b.nblocks * 64 ** 3
     lat = 4 * int(sum(int(n.prod()) for n in b.ncp))
+    # loss and gradient of the fitted lattice against the FP64 oracle:
+    # L = sum (B P - y)^2 / M and (2/M) B^T (B P - y) on 8 seeded blocks
+    import oracle
+    opt.zero_grad(set_to_none=True)
+    loss = fa.FAFitMSE.apply(ctrl, m, res, yf, plan)
+    loss.backward()
+    grad = ctrl.grad.detach().double().cpu().numpy()
+    P = ctrl.detach().double().cpu().numpy()
+    sel = np.random.Generator(np.random.PCG64(97)).permutation(b.nblocks)[:8]
+    ob = oracle.Blocks(b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots, P)
+    f = oracle.decode_blocks(ob, res, 1)
+    r = f - np.asarray(y, np.float64).reshape(b.nblocks, 1, *res)
+    loss64 = float((r * r).sum() / nvox)
+    sub = oracle.Blocks(b.ncp[sel], b.deg[sel], b.knot_off[sel], b.ctrl_off[sel], b.knots, P)
+    G = oracle.decode_adjoint(sub, res, r[sel] * (2.0 / nvox), 1)
+    gerr = 0.0
+    for k in sel:
+        o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
+        gerr = max(gerr, float(np.abs(grad[o:o + n] - G[o:o + n]).max() /
+                               np.abs(G[o:o + n]).max()))
+    err = {"loss": abs(float(loss) - loss64) / loss64, "gradient": gerr,
+           "sample": "loss over all 256 blocks; gradient max |gpu - fp64| / max |fp64| per "
+                     "block on 8 seeded blocks, at the lattice after the timed steps"}
     return _common(args, "fit iterations/sec (forward decode + MSE + HIP adjoint + Adam)",
                    1e3 / ms, "iterations/s", ms, "f32",
                    "C4 fit: 256 micro-models, NCP* per axis in {16,24,32}, cubic, 64^3 "
@@ -871,7 +911,8 @@ def bench_c4(args):
                     "graph_ms_per_step": ms_g,
                     "graph_loss_after_warmup_and_timed_replays": loss_graph,
                     "torch_composed_loss_ms_per_step": ms_t,
-                    "loss_first_last": [first, last]},
+                    "loss_first_last": [first, last],
+                    "err_vs_fp64": err},
                    ) | ({} if args.no_cpu_baseline else
                         {"cpu_baseline": cpu_baseline_fit(b, y, res, args.cpu_seconds)})
 
@@ -879,9 +920,11 @@ def bench_c4(args):
 # ------------------------------------------------------------------ C5
 
 def bench_c5(args):
+    import numpy as np
     import torch
 
     import fa_inputs as fi
+    import oracle
     import paper_2409_00184_amd as fa
     res = (64, 64, 64)
     b = fi.config_c5()
@@ -890,10 +933,29 @@ def bench_c5(args):
     out = torch.empty((b.nblocks, 4) + res, device="cuda")
     stream = torch.cuda.current_stream()
     from paper_2409_00184_amd import autotune
+    # the 1% seeded uniform subset of (block, voxel) pairs: every variant is
+    # compared on it with the FP64 oracle and with the FP32 path
+    idx = fi.voxel_subset(b.nblocks, res, 0.01, seed=55)
+    ref = oracle.decode_samples(oracle.Blocks(b.ncp, b.deg, b.knot_off, b.ctrl_off, b.knots,
+                                              b.ctrl), res, idx)
+    ti = torch.as_tensor(idx, device="cuda").long()
+    names = ["value", "d/du", "d/dv", "d/dw"]
+    scale = np.abs(ref).max(0)
+
+    def gather(inter):
+        o = out.view((b.nblocks,) + res + (4,)) if inter else out
+        if inter:
+            return o[ti[:, 0], ti[:, 1], ti[:, 2], ti[:, 3]].double().cpu().numpy()
+        return o[ti[:, 0], :, ti[:, 1], ti[:, 2], ti[:, 3]].double().cpu().numpy()
+
+    def rel(a, r):
+        return {names[c]: float(np.abs(a[:, c] - r[:, c]).max() / scale[c]) for c in range(4)}
+
     # schedules the VALU kernel is tuned over for this uniform batch
     cands = [(r, w, gr, 0, 8192, st) for r in (8, 16) for w in (4, 8) for gr in (768, 1 << 20)
              for st in (0, 1)]
     variants = {}
+    f32 = {}
     # planar [block][channel][x][y][z] output, and one 16-byte record per voxel
     for name, dtype, kernel, inter in (("f32_valu", "f32", 0, 0), ("bf16_mfma", "bf16", 1, 0),
                                        ("f16_mfma", "f16", 1, 0), ("bf16_valu", "bf16", 0, 0),
@@ -913,13 +975,19 @@ def bench_c5(args):
         ms, ev_ms, _ = timed_steps(graph.replay, max(5, args.steps // 5), 2, stream)
         del graph
         lat_b = (4 if dtype == "f32" else 2) * b.ctrl.size
-        # interleaved results are checked through a [block][x][y][z][4] view
-        chk = out.view((b.nblocks,) + res + (4,)) if inter else out
-        variants[name] = {"value": nvox / (ms * 1e-3), "ms_per_step": ms,
-                          "roofline": _roof(nvox * 16 + lat_b, ev_ms,
-                                            "decode_mfma" if kernel else "decode_sep", "c5"),
-                          "err_vs_fp64": err_vs_oracle_decode(b, chk, res, nsample=100000,
-                                                              interleaved=bool(inter))}
+        got = gather(inter)
+        if dtype == "f32":
+            f32[inter] = got
+        v = {"value": nvox / (ms * 1e-3), "ms_per_step": ms,
+             "roofline": _roof(nvox * 16 + lat_b, ev_ms,
+                               "decode_mfma" if kernel else "decode_sep", "c5"),
+             "schedule": [plan.tune.rows_per_item, plan.tune.waves, plan.ngroups,
+                          plan.tune.slab_floats, plan.tune.store],
+             "err_vs_fp64": rel(got, ref)}
+        if dtype != "f32":
+            v["diff_vs_f32_path"] = rel(got, f32[inter])
+        variants[name] = v
+    del ti
     base = variants["f32_valu"]["ms_per_step"]
     for v in variants.values():
         v["speedup_vs_f32"] = base / v["ms_per_step"]
@@ -931,9 +999,13 @@ def bench_c5(args):
                    "C5 precision: 4096 micro-models of 32^3 control points (k^-5/3), cubic, "
                    "64^3 voxels each (1.07e9), value + 3 gradients; BF16/FP16 lattices with "
                    "per-block max-abs scale on MFMA (FP32 accumulation) vs FP32",
-                   {"roofline": best["roofline"], "variants": variants})
+                   {"roofline": best["roofline"], "err_vs_fp64": best["err_vs_fp64"],
+                    "diff_vs_f32_path": best["diff_vs_f32_path"], "variants": variants,
+                    "err_sample": f"1% seeded uniform subset of (block, voxel) pairs "
+                                  f"({idx.shape[0]}), max |x - ref| / max |ref| per channel"})
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_decode(b, res, args.cpu_seconds)
+    del out
     return line
 
 
@@ -1012,7 +1084,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f1", "f2", "f3", "f4"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "c1", "c2", "c3", "c4", "c5", "f1", "f2", "f3", "f4"],
+                    help="all (default): the C2 line with C3, C4 and C5 as sub-records")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"),
@@ -1039,9 +1113,24 @@ def main():
     if args.probe:
         probe(args)
         return
-    line = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-            "c5": bench_c5, "f1": bench_f1,
-            "f2": bench_f2, "f3": bench_f3, "f4": bench_f4}[args.workload](args)
+    runs = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+            "c5": bench_c5, "f1": bench_f1, "f2": bench_f2, "f3": bench_f3, "f4": bench_f4}
+    if args.workload != "all":
+        print(json.dumps(runs[args.workload](args)), flush=True)
+        return
+    # the headline C2 line, with the other configurations of the metric as
+    # sub-records (each with its own roofline, error and oracle baseline)
+    t0 = time.perf_counter()
+    line = bench_c2(args)
+    log(f"C2 done ({time.perf_counter() - t0:.0f} s)")
+    line["workloads"] = {}
+    for w in ("c3", "c4", "c5"):
+        torch.cuda.empty_cache()
+        sub = runs[w](args)
+        for k in ("n_gpus", "steps", "warmup", "scaling", "vs_baseline", "data"):
+            sub.pop(k, None)
+        line["workloads"][w] = sub
+        log(f"{w.upper()} done ({time.perf_counter() - t0:.0f} s)")
     print(json.dumps(line), flush=True)
 
 

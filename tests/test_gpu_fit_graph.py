@@ -270,6 +270,7 @@ def test_autotune_picks_valid_schedule(fa, tmp_path, monkeypatch):
     say("autotune")
     from paper_2409_00184_amd import autotune
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "TABLE", str(tmp_path / "no_table.json"))
     b = mixed_batch(63, 40, ncp_hi=32)
     m = models(b)
     res = (32, 32, 64)
@@ -288,6 +289,7 @@ def test_autotune_interleaved_layout(fa, tmp_path, monkeypatch):
     say("autotune interleaved")
     from paper_2409_00184_amd import autotune
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "TABLE", str(tmp_path / "no_table.json"))
     b = mixed_batch(64, 24, ncp_hi=32)
     m = models(b)
     res = (32, 24, 64)
