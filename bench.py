@@ -1053,18 +1053,30 @@ def probe(args):
         run = lambda: (fa.fit(m, res, Y, workspace=fws),
                        fa.model_errors(m, res, Y, decoded=dec))
     elif w == "c5":
+        # the FP32 VALU decode at the schedule the bench times, then the
+        # BF16 matrix-core decode
+        from paper_2409_00184_amd import autotune
         b = fi.config_c5()
         m = fa.MicroModels.from_batch(b)
+        cands = [(r, wv, gr, 0, 8192, st) for r in (8, 16) for wv in (4, 8)
+                 for gr in (768, 1 << 20) for st in (0, 1)]
+        fplan = (fa.Plan(m, res, *args.probe_tune) if args.probe_tune else
+                 autotune.tune(m, res, 15, "f32", candidates=cands)[0])
         m.lattice("bf16")
         plan = fa.Plan(m, res, kernel=1)
         out = torch.empty((b.nblocks, 4) + res, device="cuda")
-        run = lambda: fa.decode(m, res, 15, dtype="bf16", plan=plan, out=out)
+        run = lambda: (fa.decode(m, res, 15, dtype="f32", plan=fplan, out=out),
+                       fa.decode(m, res, 15, dtype="bf16", plan=plan, out=out))
     else:
+        from paper_2409_00184_amd import autotune
         b = fi.config_c2() if w == "c2" else fi.config_c1()
         m = fa.MicroModels.from_batch(b)
-        plan = fa.Plan(m, res, *args.probe_tune)
-        # C2 is timed in the interleaved layout, C1 in the planar one
+        # C2 is timed in the interleaved layout, C1 in the planar one; the
+        # schedule is the one the bench times (the autotuner's table) unless
+        # --probe-tune names one
         mk = 15 | fa.OUT_INTERLEAVED if w == "c2" else 15
+        plan = (fa.Plan(m, res, *args.probe_tune) if args.probe_tune else
+                autotune.tune(m, res, mk, "f32")[0])
         out = torch.empty((b.nblocks, 4) + res, device="cuda")
         run = lambda: fa.decode(m, res, mk, plan=plan, out=out)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -1076,7 +1088,7 @@ def probe(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"probe": w, "launches": args.steps, "copy_bytes_each_way": 1 << 30,
-                      "tune": list(args.probe_tune)}))
+                      "tune": list(args.probe_tune) if args.probe_tune else "autotuner"}))
 
 
 def main():
@@ -1097,7 +1109,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--probe", action="store_true",
                     help="counter calibration run (decode launches + a 1 GiB copy)")
-    ap.add_argument("--probe-tune", type=int, nargs=6, default=[4, 4, 1 << 20, 0, 8192, 1],
+    ap.add_argument("--probe-tune", type=int, nargs=6, default=None,
                     metavar=("ROWS", "WAVES", "GRID", "KERNEL", "SLAB", "STORE"))
     args = ap.parse_args()
     if args.gpus != 1:
