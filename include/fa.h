@@ -279,21 +279,26 @@ fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t 
                          void *stream);
 
 /*
- * Adjoint of the grid decode (row a7): grad_ctrl = B^T grad_out, where B
- * is the linear map ctrl -> decode output of fa_decode_blocks for the same
- * blocks, res and mask.  Deterministic (fixed summation order, no
+ * Adjoint of the grid decode: grad_ctrl = B^T grad_out, where B is the
+ * linear map ctrl -> decode output of fa_decode_blocks for the same blocks,
+ * res and mask.  With grad_out the residual 2(f - y)/M of a least-squares
+ * fit of the lattice to samples y on the block's grid, this is the fit's
+ * gradient: the step model(NCP, degree) of Alg. 1 (Sec. 4.2.1) solves that
+ * fit for every candidate NCP.  Deterministic (fixed summation order, no
  * floating-point atomics).  A value-only cotangent (mask 1) runs on the
  * FP32 matrix cores, others on the VALU.
  *   grad_out   device FP32 [nblocks][popcount(mask)][res0][res1][res2]
  *   grad_ctrl  device FP32 lattice layout (same offsets as ctrl); the
  *              lattices of the blocks are overwritten, other elements are
  *              left untouched
- *   rows_per_item  reserved (pass 0); one workgroup streams each block
- * Requires res[1] <= 64 and res[2] <= 64 (FA_ERR_UNSUPPORTED otherwise).
+ * res[1] and res[2] (the y and z resolutions) must be at most 64: one
+ * workgroup streams each block's cotangent one x slice at a time, with the
+ * slice, its z-contracted form and the dense y and z basis matrices in LDS
+ * (FA_ERR_UNSUPPORTED above 64; res[0] takes up to FA_MAX_RES).
  */
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
                              const int32_t res[3], uint32_t mask, const float *grad_out,
-                             float *grad_ctrl, int32_t rows_per_item, void *stream);
+                             float *grad_ctrl, void *stream);
 
 /*
  * Per-block max-abs scaling and rounding to BF16/FP16 (row a4): for each
@@ -454,6 +459,34 @@ fa_status fa_ncp_search(const float *samples, int32_t nblocks, const int32_t res
  */
 fa_status fa_ncp_select(const float *errs, int32_t nblocks, int32_t ncand, int32_t ncp_lo,
                         int32_t metric, float bound, int32_t *ncp_star, int32_t *complex_);
+
+/*
+ * The cross-level step of Alg. 1 (Sec. 4.2.2), host only.  Level k of the
+ * pyramid tiles the domain with (2^k)^3 micro-blocks, block (bx, by, bz) at
+ * index (bx * 2^k + by) * 2^k + bz; its parent is the level k-1 block (bx/2,
+ * by/2, bz/2).  fa_search_set names the blocks of level `level` the in-level
+ * search runs on: every block of level 0, and a block of a finer level
+ * exactly when its parent is in the complex set of level k-1 (the blocks
+ * "covered by ComplexSet"):
+ *   parent_complex  host, (2^(k-1))^3 flags of level k-1 (ignored at k = 0)
+ *   searched        host, (2^k)^3 entries: 1 if searched, else 0
+ *   search_ids      host, may be null; receives the searched indices in
+ *                   increasing order
+ *   nsearched       receives their count
+ * fa_level_select then sets the level's outcome from the error maps of the
+ * searched blocks (laid out as fa_ncp_search writes them, one row per entry
+ * of search_ids): NCP* and the complex flag of a searched block by the rule
+ * of fa_ncp_select; every other block takes NCP* = degree + 1 and is not
+ * complex.  ncp_star and complex_ are host arrays of nblocks entries.
+ * Errors: FA_ERR_INVALID_ARG for null pointers, level outside [0, 10],
+ * search_ids not increasing or outside [0, nblocks), ncp_lo < degree + 1,
+ * an unknown metric or a non-finite bound.
+ */
+fa_status fa_search_set(int32_t level, const int32_t *parent_complex, int32_t *searched,
+                        int32_t *search_ids, int32_t *nsearched);
+fa_status fa_level_select(int32_t nblocks, const int32_t *search_ids, int32_t nsearched,
+                          const float *errs, int32_t ncand, int32_t ncp_lo, int32_t degree,
+                          int32_t metric, float bound, int32_t *ncp_star, int32_t *complex_);
 
 /*
  * Host layout of a batch of micro-models with clamped uniform knots: for

@@ -144,7 +144,11 @@ def _load():
     L.fa_store_stage.restype = ctypes.c_int
     L.fa_store_stage.argtypes = [vp, vp, i32, vp, vp, i64, vp, i64, vp, vp]
     L.fa_decode_backward.restype = ctypes.c_int
-    L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, i32, vp]
+    L.fa_decode_backward.argtypes = [vp, i32, vp, vp, u32, vp, vp, vp]
+    L.fa_search_set.restype = ctypes.c_int
+    L.fa_search_set.argtypes = [i32, vp, vp, vp, vp]
+    L.fa_level_select.restype = ctypes.c_int
+    L.fa_level_select.argtypes = [i32, vp, i32, vp, i32, i32, i32, i32, ctypes.c_float, vp, vp]
     L.fa_quantize_blocks.restype = ctypes.c_int
     L.fa_quantize_blocks.argtypes = [vp, i32, vp, ctypes.c_int, vp, vp]
     return L
@@ -360,14 +364,14 @@ def render(models, rays, width, height, tf, nb, origin, extent, block_of_cell, s
     return out
 
 
-def decode_backward(models, res, grad_out, mask=1, grad_ctrl=None, rows=0, stream=None):
+def decode_backward(models, res, grad_out, mask=1, grad_ctrl=None, stream=None):
     """Adjoint B^T g (fa_decode_backward) -> lattice-layout float32."""
     assert grad_out.dtype == torch.float32 and grad_out.is_contiguous()
     if grad_ctrl is None:
         grad_ctrl = torch.zeros_like(models.ctrl)
     st = lib.fa_decode_backward(_ptr(models.desc), models.nblocks, _ptr(models.knots),
                                 _i32x3(res), int(mask), _ptr(grad_out), _ptr(grad_ctrl),
-                                int(rows), _stream(stream))
+                                _stream(stream))
     _check("fa_decode_backward", st)
     return grad_ctrl
 
@@ -463,37 +467,62 @@ def ncp_select(errs, ncp_lo, bound, metric=METRIC_RMS):
     return nstar, cplx.astype(bool)
 
 
+def search_set(level, parent_complex=None):
+    """(searched [(2^k)^3] bool, search_ids) of Alg. 1's cross-level step
+    (fa_search_set): every block of level 0, and at a finer level the blocks
+    whose parent is complex."""
+    nb = 1 << (3 * int(level))
+    pc = (None if parent_complex is None else
+          np.ascontiguousarray(np.asarray(parent_complex).astype(np.int32)))
+    searched = np.zeros(nb, np.int32)
+    ids = np.zeros(nb, np.int32)
+    n = ctypes.c_int32(0)
+    st = lib.fa_search_set(int(level), None if pc is None else pc.ctypes.data,
+                           searched.ctypes.data, ids.ctypes.data, ctypes.byref(n))
+    _check("fa_search_set", st)
+    return searched.astype(bool), ids[:n.value].copy()
+
+
+def level_select(nblocks, search_ids, errs, ncp_lo, degree, bound, metric=METRIC_RMS):
+    """(NCP* [nb], complex [nb]) of one pyramid level (fa_level_select) from
+    the error maps of its searched blocks."""
+    ids = np.ascontiguousarray(np.asarray(search_ids, np.int32))
+    e = (None if errs is None else
+         np.ascontiguousarray(errs.cpu().numpy() if torch.is_tensor(errs) else errs, np.float32))
+    ncand = int(e.shape[1]) if e is not None and e.size else 1
+    nstar = np.zeros(int(nblocks), np.int32)
+    cplx = np.zeros(int(nblocks), np.int32)
+    st = lib.fa_level_select(int(nblocks), ids.ctypes.data if ids.size else None, int(ids.size),
+                             e.ctypes.data if e is not None and e.size else None, ncand,
+                             int(ncp_lo), int(degree), int(metric), float(bound),
+                             nstar.ctypes.data, cplx.ctypes.data)
+    _check("fa_level_select", st)
+    return nstar, cplx.astype(bool)
+
+
 def adaptive_encode(levels, degree, bound, metric=METRIC_RMS, ncp_lo=None, ncp_hi=None):
     """Cross-level adaptive encoding (Alg. 1) over a pyramid of micro-blocks.
 
     levels[k]: samples [(2^k)^3, R, R, R] float32 on the GPU, level 0 the
     coarsest, block (bx, by, bz) of level k at (bx * 2^k + by) * 2^k + bz.
-    Level 0 is searched in full; a block of level k > 0 is searched only if
-    its parent is complex, otherwise it takes NCP* = degree + 1.  Every block
-    is then fitted at its NCP*.  Returns, per level, a dict with ncp_star,
-    complex, searched (numpy) and the fitted MicroModels."""
+    Per level: fa_search_set names the blocks to search, fa_ncp_search
+    builds their error maps, fa_level_select sets NCP* and the complex set,
+    and every block is fitted at its NCP* (fa_fit_blocks).  Returns, per
+    level, a dict with ncp_star, complex, searched (numpy) and the fitted
+    MicroModels."""
     out = []
     prev = None
     for k, Y in enumerate(levels):
         nb, R = Y.shape[0], int(Y.shape[1])
         lo = degree + 2 if ncp_lo is None else int(ncp_lo)
         hi = R if ncp_hi is None else int(ncp_hi)
-        nstar = np.full(nb, degree + 1, np.int32)
-        cplx = np.zeros(nb, bool)
-        if k == 0:
-            searched = np.ones(nb, bool)
-        else:
-            m = 1 << k
-            b = np.arange(nb)
-            bx, by, bz = b // (m * m), (b // m) % m, b % m
-            parent = ((bx // 2) * (m // 2) + by // 2) * (m // 2) + bz // 2
-            searched = prev[parent]
-        idx = np.nonzero(searched)[0]
-        if idx.size:
-            sub = Y[torch.as_tensor(idx, device=Y.device)].contiguous()
+        searched, ids = search_set(k, prev)
+        assert searched.size == nb, "level k holds (2^k)^3 blocks"
+        errs = None
+        if ids.size:
+            sub = Y[torch.as_tensor(ids, device=Y.device).long()].contiguous()
             errs = ncp_search(sub, degree, lo, hi)
-            ns, cx = ncp_select(errs, lo, bound, metric)
-            nstar[idx], cplx[idx] = ns, cx
+        nstar, cplx = level_select(nb, ids, errs, lo, degree, bound, metric)
         models = uniform_models(np.repeat(nstar[:, None], 3, 1), np.full(nb, degree))
         fit(models, Y.shape[1:], Y.contiguous())
         out.append(dict(ncp_star=nstar, complex=cplx, searched=searched, models=models))

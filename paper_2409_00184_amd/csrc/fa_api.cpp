@@ -502,14 +502,13 @@ fa_status fa_visible_cells(const fa_ray *rays, int32_t width, int32_t height, in
 
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,
                              const int32_t res[3], uint32_t mask, const float *grad_out,
-                             float *grad_ctrl, int32_t rows_per_item, void *stream) {
+                             float *grad_ctrl, void *stream) {
     if (!blocks || nblocks <= 0 || !knots || !res_ok(res) || !grad_out || !grad_ctrl ||
-        (mask & 15u) == 0 || (mask & ~15u) != 0 || rows_per_item < 0)
+        (mask & 15u) == 0 || (mask & ~15u) != 0)
         return FA_ERR_INVALID_ARG;
     if (!res_supported(res) || res[1] > 64 || res[2] > 64) return FA_ERR_UNSUPPORTED;
     hipError_t e = launch_adjoint(blocks, nblocks, knots, res[0], res[1], res[2], mask,
-                                  grad_out, grad_ctrl, rows_per_item ? rows_per_item : 2,
-                                  (hipStream_t)stream);
+                                  grad_out, grad_ctrl, 0, (hipStream_t)stream);
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
@@ -686,6 +685,59 @@ fa_status fa_ncp_select(const float *errs, int32_t nblocks, int32_t ncand, int32
         }
         ncp_star[b] = ncp_lo + (best >= 0 ? best : ncand - 1);
         if (complex_) complex_[b] = over ? 1 : 0;
+    }
+    return FA_OK;
+}
+
+fa_status fa_search_set(int32_t level, const int32_t *parent_complex, int32_t *searched,
+                        int32_t *search_ids, int32_t *nsearched) {
+    if (level < 0 || level > 10 || !searched || !nsearched || (level > 0 && !parent_complex))
+        return FA_ERR_INVALID_ARG;
+    const int m = 1 << level, h = m >> 1;
+    const int64_t nb = (int64_t)m * m * m;
+    int32_t count = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int32_t on = 1;
+        if (level > 0) {
+            const int bx = (int)(b / ((int64_t)m * m)), by = (int)((b / m) % m), bz = (int)(b % m);
+            const int64_t parent = ((int64_t)(bx / 2) * h + by / 2) * h + bz / 2;
+            on = parent_complex[parent] != 0;
+        }
+        searched[b] = on;
+        if (on) {
+            if (search_ids) search_ids[count] = (int32_t)b;
+            ++count;
+        }
+    }
+    *nsearched = count;
+    return FA_OK;
+}
+
+fa_status fa_level_select(int32_t nblocks, const int32_t *search_ids, int32_t nsearched,
+                          const float *errs, int32_t ncand, int32_t ncp_lo, int32_t degree,
+                          int32_t metric, float bound, int32_t *ncp_star, int32_t *complex_) {
+    if (nblocks <= 0 || nsearched < 0 || nsearched > nblocks || (nsearched > 0 && !search_ids) ||
+        (nsearched > 0 && !errs) || ncand <= 0 || degree < 1 || ncp_lo < degree + 1 ||
+        !ncp_star || !complex_ || (metric != 0 && metric != 1) || !std::isfinite(bound))
+        return FA_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < nsearched; ++i)
+        if (search_ids[i] < 0 || search_ids[i] >= nblocks || (i > 0 && search_ids[i] <= search_ids[i - 1]))
+            return FA_ERR_INVALID_ARG;
+    // searched blocks first into scratch of the caller's outputs: the
+    // selection rule of fa_ncp_select, then scattered to their indices
+    std::vector<int32_t> ns(nsearched), cx(nsearched);
+    if (nsearched > 0) {
+        const fa_status st = fa_ncp_select(errs, nsearched, ncand, ncp_lo, metric, bound,
+                                           ns.data(), cx.data());
+        if (st != FA_OK) return st;
+    }
+    for (int32_t b = 0; b < nblocks; ++b) {
+        ncp_star[b] = degree + 1;
+        complex_[b] = 0;
+    }
+    for (int32_t i = 0; i < nsearched; ++i) {
+        ncp_star[search_ids[i]] = ns[i];
+        complex_[search_ids[i]] = cx[i];
     }
     return FA_OK;
 }

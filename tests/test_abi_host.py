@@ -217,8 +217,8 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     a = list(args(4, 4, rp))
     a[13] = None  # no transfer function
     assert L.fa_render_rays(*a) == 1
-    assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, 0, None) == 2
-    assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, 0, None) == 1
+    assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, None) == 2
+    assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
     # the allocation-free residual: bad arguments, then a batch whose work
     # items exceed its fixed scratch array, both before any device call

@@ -152,3 +152,4 @@ def test_cross_level_searches_only_children_of_complex_blocks():
     assert set(np.nonzero(s2)[0]) == set(kids)
     others = np.setdiff1d(np.arange(64), kids)
     assert np.all(n2[others] == p + 1)
+
