@@ -45,15 +45,19 @@ CANDIDATES = _candidates()
 
 def signature(models, res, mask, dtype):
     """Hash of the multiset of (NCP_x, NCP_y, NCP_z, degree) rows of the
-    batch, the resolution, mask, dtype and device name."""
+    batch, the resolution, mask, dtype and the device's architecture and
+    compute-unit count (the marketing name differs between otherwise equal
+    boards)."""
     d = models.host_desc
     rows = np.concatenate([d["ncp"], d["degree"][:, :1]], axis=1).astype(np.int32)
     uniq, cnt = np.unique(rows, axis=0, return_counts=True)
     h = hashlib.sha1()
     h.update(uniq.tobytes())
     h.update(cnt.astype(np.int64).tobytes())
-    h.update(repr((tuple(int(r) for r in res), int(mask), dtype,
-                   torch.cuda.get_device_name())).encode())
+    props = torch.cuda.get_device_properties(models.device)
+    arch = getattr(props, "gcnArchName", "").split(":")[0]
+    h.update(repr((tuple(int(r) for r in res), int(mask), dtype, arch,
+                   int(props.multi_processor_count))).encode())
     return h.hexdigest()[:20]
 
 

@@ -58,7 +58,8 @@ __device__ __forceinline__ f32x4a mma4(float a, float b, const f32x4a &c) {
 }
 
 template <int P, int TW>
-__device__ void adj_value_block(const fa_block &B, const float *knots, int rx, int ry, int rz,
+__device__ __forceinline__ void adj_value_block(const fa_block &B, const float *knots, int rx,
+                                                int ry, int rz,
                                 const float *g, float *G, int b, AmSmem &sm) {
     constexpr int R = P + 1;  // ring slots
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -202,13 +203,28 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
             const int ao = (16 * mt + l16) * kSS + gq;
             const float *ga0 = sm.g[b0] + ao, *ga1 = sm.g[b0 + 1] + ao;
             const float *bz = sm.Bz + gq * kTS + 16 * nt + l16;
-            // K steps of 4 positions covering the tile's band (none if empty)
-            f32x4a z0 = {0.0f, 0.0f, 0.0f, 0.0f}, z1 = z0;
-            for (int st = sm.tw[0][nt] >> 2; st <= (sm.tw[1][nt] >> 2); ++st) {
+            // K steps of 4 positions covering the tile's band (none if empty),
+            // even and odd steps in separate chains (four independent chains
+            // per wave hide the matrix cores' latency), added at the end
+            f32x4a z0 = {0.0f, 0.0f, 0.0f, 0.0f}, z1 = z0, z0o = z0, z1o = z0;
+            const int s1 = sm.tw[1][nt] >> 2;
+            int st = sm.tw[0][nt] >> 2;
+            for (; st + 1 <= s1; st += 2) {
+                const float bb = bz[4 * st * kTS], bo = bz[4 * (st + 1) * kTS];
+                const float a0 = ga0[4 * st], a1 = ga1[4 * st];
+                const float o0 = ga0[4 * (st + 1)], o1 = ga1[4 * (st + 1)];
+                z0 = mma4(a0, bb, z0);
+                z1 = mma4(a1, bb, z1);
+                z0o = mma4(o0, bo, z0o);
+                z1o = mma4(o1, bo, z1o);
+            }
+            if (st <= s1) {
                 const float bb = bz[4 * st * kTS];
                 z0 = mma4(ga0[4 * st], bb, z0);
                 z1 = mma4(ga1[4 * st], bb, z1);
             }
+            z0 += z0o;
+            z1 += z1o;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int zo = (16 * mt + 4 * gq + r) * kTS + 16 * nt + l16;
@@ -227,18 +243,34 @@ __device__ void adj_value_block(const fa_block &B, const float *knots, int rx, i
             const int mt = tt % njt, nt = tt / njt;
             const float *by = sm.By + gq * kTS + 16 * mt + l16;
             const int zo = gq * kTS + 16 * nt + l16;
-            for (int st = sm.tv[0][mt] >> 2; st <= (sm.tv[1][mt] >> 2); ++st) {
+            f32x4a y0o = {0.0f, 0.0f, 0.0f, 0.0f}, y1o = y0o;
+            const int s1 = sm.tv[1][mt] >> 2;
+            int st = sm.tv[0][mt] >> 2;
+            for (; st + 1 <= s1; st += 2) {
+                const float aa = by[4 * st * kTS], ao = by[4 * (st + 1) * kTS];
+                const float b0 = sm.Z[0][zo + 4 * st * kTS], b1 = sm.Z[1][zo + 4 * st * kTS];
+                const float o0 = sm.Z[0][zo + 4 * (st + 1) * kTS];
+                const float o1 = sm.Z[1][zo + 4 * (st + 1) * kTS];
+                y0[t] = mma4(aa, b0, y0[t]);
+                y1[t] = mma4(aa, b1, y1[t]);
+                y0o = mma4(ao, o0, y0o);
+                y1o = mma4(ao, o1, y1o);
+            }
+            if (st <= s1) {
                 const float aa = by[4 * st * kTS];
                 y0[t] = mma4(aa, sm.Z[0][zo + 4 * st * kTS], y0[t]);
                 y1[t] = mma4(aa, sm.Z[1][zo + 4 * st * kTS], y1[t]);
             }
+            y0[t] += y0o;
+            y1[t] += y1o;
         }
         accumulate(u, y0);
         if (two) accumulate(u + 1, y1);
         // slices u+2, u+3 (loaded while this pair was contracted) into the
         // other pair of buffers, u+4, u+5 into flight; the registers are
         // written only by the loads, so waiting for them never waits for
-        // the newer ones
+        // the newer ones (a deeper ring of three pairs in registers was
+        // measured slower: 0.152 against 0.130 ms on C4)
         put(b0 ^ 2, pf[0]);
         put((b0 ^ 2) + 1, pf[1]);
         fetch(u + 4, pf[0]);

@@ -21,7 +21,8 @@ def test_refuses_more_than_one_gpu():
 
 @pytest.mark.parametrize("kernel,workload", [("decode_sep", "c2"), ("query", "c3"),
                                              ("adjoint", "c4"), ("decode_mfma", "c5"),
-                                             ("render", "f1"), ("fit", "f2")])
+                                             ("render", "f1"), ("fit", "f2"),
+                                             ("decode_sep", "c5")])
 def test_traffic_files_match_sources(kernel, workload):
     """Every committed traffic summary was taken on the kernel sources in the
     tree (a kernel changed since its counters were read must be profiled
