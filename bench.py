@@ -252,8 +252,10 @@ def bench_c2(args):
         "data": "synthetic",
         "config": {"workload": "C2 batched decode: 512 micro-models, NCP* per axis in "
                                "{8,12,16,24,32}, degree in {2,3}, 64^3 voxels each, value + 3 "
-                               "gradients, FP32, one persistent launch replayed from a HIP "
-                               "graph, one 16-byte record per voxel",
+                               "gradients, FP32, one launch over the batch plan's work items "
+                               "in longest-first order at the autotuner's schedule (one "
+                               "workgroup per item), replayed from a HIP graph, one 16-byte "
+                               "record per voxel",
                    "nblocks": batch.nblocks, "res": list(res), "channels": 4,
                    "layout": "[block][x][y][z][value, d/du, d/dv, d/dw]",
                    "schedule": {"rows_per_item": plan.tune.rows_per_item,
@@ -272,6 +274,21 @@ def bench_c2(args):
                    "schedule": [pplan.tune.rows_per_item, pplan.tune.waves, pplan.ngroups,
                                 pplan.tune.slab_floats, pplan.tune.store]},
     }
+    # the persistent form of the plan (a fixed number of workgroups, each
+    # running its longest-first share of the items) beside the timed one
+    pers = []
+    t = plan.tune
+    for grid in (512, 768, 1024, 1536, 2048):
+        pp = fa.Plan(m, res, t.rows_per_item, t.waves, grid, 0, t.slab_floats, t.store)
+        o3 = torch.empty((batch.nblocks,) + res + (4,), dtype=torch.float32, device="cuda")
+        g3, _ = fa.capture(lambda: fa.decode(m, res, mask, plan=pp, out=o3))
+        pms3 = timed_steps(g3.replay, args.steps, args.warmup, stream)[0]
+        pers.append((pms3, grid))
+        del g3, o3
+    pms3, pgrid = min(pers)
+    line["persistent"] = {"value": nvox / (pms3 * 1e-3), "ms_per_step": pms3,
+                          "workgroups": pgrid, "vs_timed": ms / pms3,
+                          "grids_tried": {str(g): v for v, g in pers}}
     if not args.no_plain:
         pms, pev, _ = timed_steps(lambda: fa.decode_plain(m, res, 15, out=out),
                                   max(2, args.steps // 10), 1, stream)
