@@ -449,6 +449,27 @@ def bench_c3(args):
                                                np.abs(ref[:, c]).max())
                                       for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}}
         line["lowp"] = lp
+    # the same tiling and camera with every interior knot jittered (binary
+    # span search instead of the uniform-knot guess)
+    bn = fi.config_c3_blocks(nonuniform=True)
+    mn = fa.MicroModels.from_batch(bn)
+    fnu = lambda: fa.query_rays(mn, xyz, 1920, 1080, 512, (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                                boc, out=out)
+    graph, _ = fa.capture(fnu)
+    nms, nev, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph
+    fnu()
+    torch.cuda.synchronize()
+    gn = out[idx].double().cpu().numpy()
+    obn = oracle.Blocks(bn.ncp, bn.deg, bn.knot_off, bn.ctrl_off, bn.knots, bn.ctrl)
+    refn = oracle.query_points(obn, xs, (16, 16, 16), (0, 0, 0), (1, 1, 1),
+                               fi.identity_cells(4096))
+    line["nonuniform_knots"] = {
+        "value": n / (nms * 1e-3), "ms_per_step": nms, "avg_launch_ms": nev,
+        "vs_uniform": ms / nms,
+        "err_vs_fp64": {k: float(np.abs(gn[:, c] - refn[:, c]).max() / np.abs(refn[:, c]).max())
+                        for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}}
+    del mn
     if not args.no_cpu_baseline:
         k_max = 20_000_000
         sidx = torch.as_tensor(g.integers(0, n, k_max), device="cuda")

@@ -201,19 +201,36 @@ def config_c2(seed=2, nblocks=512, ncp_choices=NCP_CHOICES_C2, deg_choices=(2, 3
     return out
 
 
-def config_c3_blocks(seed=3, nb=16, ncp_lo=8, ncp_hi=32, p=3):
+def jittered_knots(g, n, p, amount=0.3):
+    """Clamped knots on [0, 1] whose interior knots are the uniform ones
+    moved by up to amount/2 of a knot spacing each way (non-uniform, strictly
+    increasing), FP32."""
+    t = clamped_uniform_knots(n, p).astype(np.float64)
+    h = 1.0 / (n - p)
+    m = n - p - 1
+    if m > 0:
+        t[p + 1:n] += g.uniform(-0.5 * amount * h, 0.5 * amount * h, m)
+    return t.astype(np.float32)
+
+
+def config_c3_blocks(seed=3, nb=16, ncp_lo=8, ncp_hi=32, p=3, nonuniform=False):
     """nb^3 blocks tiling [0,1]^3; n_a ~ U{ncp_lo..ncp_hi}; one global
-    sinusoid field (k in cycles per block) so neighbours agree at faces."""
+    sinusoid field (k in cycles per block) so neighbours agree at faces.
+    nonuniform: every interior knot jittered (jittered_knots), drawn from a
+    stream of its own so the NCP draws and the field stay those of the
+    uniform configuration."""
     g = rng(seed)
     k, phi = sinusoid_params(g)
     ncp = g.integers(ncp_lo, ncp_hi + 1, size=(nb ** 3, 3))
+    gk = rng(seed + 1000)
     kl, lat = [], []
     for bx in range(nb):
         for by in range(nb):
             for bz in range(nb):
                 b = (bx * nb + by) * nb + bz
                 n = tuple(int(v) for v in ncp[b])
-                ts = [clamped_uniform_knots(n[a], p) for a in range(3)]
+                ts = [jittered_knots(gk, n[a], p) if nonuniform else
+                      clamped_uniform_knots(n[a], p) for a in range(3)]
                 kl.append(ts)
                 # block-local xi in [0,1] -> field coordinate (b + xi) in blocks
                 lat.append(sinusoid_lattice(k, phi, ts[0], ts[1], ts[2], n, (p, p, p),

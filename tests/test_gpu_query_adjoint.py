@@ -111,6 +111,52 @@ def test_query_rays_matches_flat(fa, w, h, k):
         check_elementwise_bound(rays.cpu().numpy(), r, S, 64.0, "rays")
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_query_rays_low_precision_and_nonuniform(fa, dtype):
+    """The ray order on 2-byte lattices (rows read from the LDS slots as
+    dword pairs) and on blocks with non-uniform knots (binary span search on
+    the knots in LDS), including blocks larger than one LDS slot (the
+    per-lane fallback): bit for bit the flat query, which the oracle
+    checks."""
+    say("query rays lowp / nonuniform", dtype)
+    g = fi.rng(47)
+    nb = (4, 4, 4)
+    ncp, deg, kl, lat = [], [], [], []
+    for k in range(64):
+        p = int(g.choice([2, 3]))
+        n = [int(v) for v in g.integers(p + 1, 33, 3)]
+        if k == 5:
+            n = [40, 30, 20]  # 24000 lattice values: above one LDS slot in FP32
+        ks = []
+        for a in range(3):
+            if k % 3 == 0 and n[a] > p + 1:
+                inner = np.sort(g.uniform(0.02, 0.98, n[a] - p - 1))
+                ks.append(np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)]).astype(np.float32))
+            else:
+                ks.append(fi.clamped_uniform_knots(n[a], p))
+        ncp.append(n)
+        deg.append((p, p, p))
+        kl.append(ks)
+        lat.append(g.normal(size=n))
+    b = fi.pack(ncp, deg, kl, lat)
+    m = models(b)
+    w, h, k = 96, 40, 48
+    o, d, t0, t1, j = fi.camera_rays(48, w, h)
+    s = np.arange(k)
+    t = t0[:, None] + (s[None] + j[:, None]) / k * (t1 - t0)[:, None]
+    xyz = torch.as_tensor((o[:, None] + d[:, None] * t[..., None]).reshape(-1, 3)
+                          .astype(np.float32)).cuda()
+    boc = torch.as_tensor(np.arange(64, dtype=np.int32), device="cuda")
+    for dt in ("f32", dtype):
+        flat = fa.query(m, xyz, nb, (0, 0, 0), (1, 1, 1), boc, dtype=dt)
+        rays = fa.query_rays(m, xyz, w, h, k, nb, (0, 0, 0), (1, 1, 1), boc, dtype=dt)
+        assert torch.equal(flat, rays), dt
+    r, S = oracle.query_points(oracle_blocks(b), xyz.cpu().numpy(), nb, (0, 0, 0), (1, 1, 1),
+                               np.arange(64, dtype=np.int32), with_abs=True)
+    check_elementwise_bound(fa.query_rays(m, xyz, w, h, k, nb, (0, 0, 0), (1, 1, 1), boc)
+                            .cpu().numpy(), r, S, 64.0, "rays nonuniform f32")
+
+
 def test_query_c3_full_sampled(fa):
     """C3 at full size: 1920x1080 rays x 512 samples generated on the GPU
     (1.06e9 samples); 300k sampled outputs checked against the oracle."""

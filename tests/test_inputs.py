@@ -60,3 +60,16 @@ def test_voxel_subset_is_a_seeded_sample_without_replacement():
     assert np.array_equal(s, fi.voxel_subset(7, (5, 6, 9), frac=0.1, seed=3))
     # 1% of C5's 4096 x 64^3 pairs
     assert int(4096 * 64 ** 3 * 0.01) == 10_737_418
+
+
+def test_jittered_knots_nonuniform_and_increasing():
+    g = fi.rng(5)
+    for n, p in ((8, 3), (32, 3), (12, 2), (4, 3)):
+        t = fi.jittered_knots(g, n, p)
+        assert t.dtype == np.float32 and len(t) == n + p + 1
+        assert np.all(t[:p + 1] == 0) and np.all(t[n:] == 1)
+        assert np.all(np.diff(t[p:n + 1]) > 0)
+        if n - p > 1:
+            assert not np.array_equal(t, fi.clamped_uniform_knots(n, p))
+    a, b = fi.config_c3_blocks(nb=2), fi.config_c3_blocks(nb=2, nonuniform=True)
+    assert np.array_equal(a.ncp, b.ncp) and not np.array_equal(a.knots, b.knots)
