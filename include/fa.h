@@ -285,15 +285,18 @@ fa_status fa_render_rays(const fa_block *blocks, int32_t nblocks, const int32_t 
  * fit of the lattice to samples y on the block's grid, this is the fit's
  * gradient: the step model(NCP, degree) of Alg. 1 (Sec. 4.2.1) solves that
  * fit for every candidate NCP.  Deterministic (fixed summation order, no
- * floating-point atomics).  A value-only cotangent (mask 1) runs on the
- * FP32 matrix cores, others on the VALU.
+ * floating-point atomics).  A value-only cotangent (mask 1) whose rows start
+ * on 16-byte boundaries (res[2] a multiple of 4, grad_out 16-byte aligned)
+ * runs on the FP32 matrix cores; other cotangents run on the VALU.
  *   grad_out   device FP32 [nblocks][popcount(mask)][res0][res1][res2]
  *   grad_ctrl  device FP32 lattice layout (same offsets as ctrl); the
  *              lattices of the blocks are overwritten, other elements are
  *              left untouched
  * res[1] and res[2] (the y and z resolutions) must be at most 64: one
- * workgroup streams each block's cotangent one x slice at a time, with the
- * slice, its z-contracted form and the dense y and z basis matrices in LDS
+ * workgroup streams each block's cotangent one x slice at a time, the
+ * matrix-core form holding a slice's y and z extent as four 16-row bands of
+ * four 16-column groups in registers, the VALU form holding the slice, its
+ * z-contracted form and the dense y and z basis matrices in LDS
  * (FA_ERR_UNSUPPORTED above 64; res[0] takes up to FA_MAX_RES).
  */
 fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const float *knots,

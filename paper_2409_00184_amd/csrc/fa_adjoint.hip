@@ -271,8 +271,10 @@ __global__ __launch_bounds__(64 * adj_waves<DER>()) void adjoint_kernel(
 hipError_t launch_adjoint(const fa_block *blocks, int nblocks, const float *knots, int rx,
                           int ry, int rz, uint32_t mask, const float *g, float *G, int /*it*/,
                           hipStream_t s) {
-    if ((mask & 15u) == 1u)  // the value channel alone: the matrix-core form
-        return launch_adjoint_value(blocks, nblocks, knots, rx, ry, rz, g, G, s);
+    if ((mask & 15u) == 1u) {  // the value channel alone: the matrix-core form
+        const hipError_t e = launch_adjoint_value(blocks, nblocks, knots, rx, ry, rz, g, G, s);
+        if (e != hipErrorNotSupported) return e;  // else rows it cannot load as 16-byte vectors
+    }
     const int nch = __builtin_popcount(mask & 15u);  // derivative channels present
     // raise the dynamic LDS limit once per process (before any graph capture)
     static const hipError_t attr = hipFuncSetAttribute(

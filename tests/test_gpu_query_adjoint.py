@@ -208,12 +208,16 @@ def test_adjoint_vs_oracle(fa, mask, res):
         assert err <= 1e-5 * np.abs(Gr[o:o + k]).max(), (bb, err)
 
 
-@pytest.mark.parametrize("res", [(19, 64, 64), (33, 37, 50)])
+@pytest.mark.parametrize("res", [(19, 64, 64), (33, 37, 50), (65, 33, 36), (19, 8, 8)])
 def test_adjoint_wide_lattices_vs_oracle(fa, res):
-    """Value cotangents of lattices with NCP_y or NCP_z above 32 (more than
-    eight 16 x 16 output tiles: the two-tile matrix-core kernel) next to
-    narrow ones (the one-tile kernel) in one batch, and NCP_x above the x
-    resolution (several control planes complete per x slice)."""
+    """Value cotangents of lattices with NCP_y or NCP_z above 32 (several
+    j and k tiles per micro-model) next to narrow ones in one batch, NCP_x
+    above the x resolution (several control planes complete per x slice,
+    and planes between the x chunks of two waves that no slice touches),
+    y and z resolutions that are not multiples of 16 (partial row bands and
+    column groups), and z resolutions that are not multiples of 4 (rows
+    that the matrix-core kernel cannot read as 16-byte vectors: the VALU
+    adjoint)."""
     say("adjoint wide", res)
     g = fi.rng(45)
     ncp = [(8, 40, 36), (6, 33, 20), (5, 10, 64), (12, 24, 24), (40, 12, 8), (7, 64, 33)]

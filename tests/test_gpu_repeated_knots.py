@@ -129,12 +129,14 @@ def test_query_on_repeated_knots(fa):
             check_elementwise_bound(q, r, S, 64.0, f"repeated knots query block {k} mask {mask}")
 
 
+@pytest.mark.parametrize("res", [(65, 33, 33), (33, 33, 64)])
 @pytest.mark.parametrize("mask", [1, 15])
-def test_adjoint_repeated_knots(fa, mask):
-    say("repeated knots adjoint", mask)
+def test_adjoint_repeated_knots(fa, mask, res):
+    """res[2] = 64: the value adjoint on the matrix cores (16-byte rows);
+    33: the VALU adjoint.  The adjoint takes y and z resolutions up to 64."""
+    say("repeated knots adjoint", mask, res)
     b = repeated_batch(95)
     m = models(b)
-    res = (65, 33, 33)  # the adjoint takes y and z resolutions up to 64
     nchan = bin(mask).count("1")
     g = torch.randn((b.nblocks, nchan) + res, generator=torch.Generator().manual_seed(96))
     G = fa.decode_backward(m, res, g.cuda().contiguous(), mask).cpu().numpy()
