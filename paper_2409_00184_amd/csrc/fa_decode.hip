@@ -208,9 +208,9 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
 #pragma unroll
         for (int r = 0; r <= P; ++r) wBB[r] = wDB[r] = wBD[r] = 0.0f;
         int top = -1;
-        // residual form: the sample of x position u, loaded two positions
-        // ahead into one of two registers used alternately (no register
-        // copy waits for a load in flight)
+        // residual form: the sample of x position u, loaded four positions
+        // ahead into one of four registers used in turn (no register copy
+        // waits for a load in flight)
         auto yload = [&](int u) {
             return RESID ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                                                          yr, (live && u < a.rx)
@@ -225,10 +225,17 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
         auto ydummy = [&]() {
             if (GRAD) __builtin_amdgcn_raw_buffer_store_b32(0u, gr, kDead, 0, 0);
         };
-        float y0 = yload(0);
-        ydummy();
-        float y1 = yload(1);
-        ydummy();
+        float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
+        if constexpr (RESID) {
+            y0 = yload(0);
+            ydummy();
+            y1 = yload(1);
+            ydummy();
+            y2 = yload(2);
+            ydummy();
+            y3 = yload(3);
+            ydummy();
+        }
 
         auto step = [&](int u, float &ycur) {
             const int s = sm.xS[u];
@@ -288,7 +295,7 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
                 // old and new values never live at once (no copy)
                 const float r = val - ycur;
                 const uint32_t off = col_off + (uint32_t)u * pstep;
-                ycur = yload(u + 2);
+                ycur = yload(u + 4);
                 const double rd = live ? (double)r : 0.0;
                 acc = fma(rd, rd, acc);
                 if (GRAD)
@@ -320,11 +327,23 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
             }
         };
         int u = 0;
-        for (; u + 1 < a.rx; u += 2) {
-            step(u, y0);
-            step(u + 1, y1);
+        if constexpr (RESID) {
+            for (; u + 3 < a.rx; u += 4) {
+                step(u, y0);
+                step(u + 1, y1);
+                step(u + 2, y2);
+                step(u + 3, y3);
+            }
+            if (u < a.rx) step(u, y0);
+            if (u + 1 < a.rx) step(u + 1, y1);
+            if (u + 2 < a.rx) step(u + 2, y2);
+        } else {  // no samples: two steps per iteration keep the code small
+            for (; u + 1 < a.rx; u += 2) {
+                step(u, y0);
+                step(u + 1, y1);
+            }
+            if (u < a.rx) step(u, y0);
         }
-        if (u < a.rx) step(u, y0);
       };
         if (single) walk(std::true_type{});
         else walk(std::false_type{});
