@@ -216,65 +216,94 @@ struct FitZSmem {
 };
 
 // T[b][k][l] = sum_z X_z[k][z] y[b][l][z], l = x * R1 + y: per chunk of 128
-// lines, a (n_z x R2) x (R2 x 128) product on the FP64 matrix cores.
+// lines, a (n_z x R2) x (R2 x 128) product on the FP64 matrix cores.  A
+// workgroup takes `cgroup` consecutive chunks of one block: X_z is staged
+// once, and the next chunk's samples are loaded into registers while the
+// products of the current one run.
+constexpr int kZRegs = kZLines * kFitR / kFitThreads;  // chunk floats per thread
+
 __global__ __launch_bounds__(kFitThreads) void fit_z_kernel(const fa_block *blocks, int nblocks,
                                                             const float *knots, int r0, int r1,
-                                                            int r2, int max_n, const float *y,
-                                                            const double *Xg, int64_t xstride,
-                                                            double *T) {
+                                                            int r2, int max_n, int cgroup,
+                                                            const float *y, const double *Xg,
+                                                            int64_t xstride, double *T) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FitZSmem &sm = *reinterpret_cast<FitZSmem *>(smem_raw);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int64_t lines = (int64_t)r0 * r1;
     const int chunks = (int)((lines + kZLines - 1) / kZLines);
-    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * chunks; item += gridDim.x) {
-        const int bi = (int)(item / chunks);
-        const int64_t l0 = (item - (int64_t)bi * chunks) * kZLines;
+    const int groups = (chunks + cgroup - 1) / cgroup;
+    for (int64_t item = blockIdx.x; item < (int64_t)nblocks * groups; item += gridDim.x) {
+        const int bi = (int)(item / groups);
+        const int c0 = (int)(item - (int64_t)bi * groups) * cgroup;
+        const int c1 = min(chunks, c0 + cgroup);
         const fa_block b = blocks[bi];
         const int nz = b.ncp[2];
         if (nz > max_n) continue;  // the workspace has no room; the lattice is left as is
+        __syncthreads();  // the previous item is done with the LDS
         const double *Xz = Xg + (int64_t)bi * xstride + 2 * kPinvStride;
         for (int e = tid; e < nz * kFitR; e += kFitThreads) {
             const int k = e / kFitR;
             sm.X[k][e - k * kFitR] = Xz[e];
         }
-        const int cl = (int)(lines - l0 < kZLines ? lines - l0 : kZLines);
-        const float *yb = y + ((int64_t)bi * lines + l0) * r2;
-        for (int e = tid; e < cl * r2; e += kFitThreads) {
-            const int li = e / r2;
-            sm.ys[li][e - li * r2] = yb[e];
-        }
-        __syncthreads();
-        const int mt = (nz + 15) >> 4, nt = (cl + 15) >> 4, ksteps = (r2 + 3) >> 2;
-        const int nst = (nt + 3) >> 2;  // strips of 4 line tiles sharing the A operand
-        double *Tb = T + (int64_t)bi * max_n * lines + l0;
-        for (int unit = wave; unit < mt * nst; unit += kFitThreads / 64) {
-            const int ti = unit / nst, tj0 = 4 * (unit - ti * nst);
-            const int k = 16 * ti + lr;
-            f64x4 acc[4];
+        // chunk c in registers: element e = tid + kFitThreads m of its cl x r2 samples
+        float yv[kZRegs];
+        auto fetch = [&](int c) {
+            const int64_t l0 = (int64_t)c * kZLines;
+            const int cl = (int)(lines - l0 < kZLines ? lines - l0 : kZLines);
+            const float *yb = y + ((int64_t)bi * lines + l0) * r2;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < ksteps; ++ks) {
-                const int z = 4 * ks + lk;
-                const bool zok = z < r2;
-                const double av = (k < nz && zok) ? sm.X[k][z] : 0.0;
+            for (int m = 0; m < kZRegs; ++m) {
+                const int e = tid + kFitThreads * m;
+                yv[m] = (c < c1 && e < cl * r2) ? yb[e] : 0.0f;
+            }
+        };
+        fetch(c0);
+        const int mt = (nz + 15) >> 4, ksteps = (r2 + 3) >> 2;
+        for (int c = c0; c < c1; ++c) {
+            const int64_t l0 = (int64_t)c * kZLines;
+            const int cl = (int)(lines - l0 < kZLines ? lines - l0 : kZLines);
+            if (c > c0) __syncthreads();  // the previous chunk's products are done
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int li = 16 * (tj0 + q) + lr;
-                    const double bv = (li < cl && zok) ? (double)sm.ys[li][z] : 0.0;
-                    acc[q] = mfma64(av, bv, acc[q]);  // four independent chains
+            for (int m = 0; m < kZRegs; ++m) {
+                const int e = tid + kFitThreads * m;
+                if (e < cl * r2) {
+                    const int li = e / r2;
+                    sm.ys[li][e - li * r2] = yv[m];
                 }
             }
+            __syncthreads();
+            fetch(c + 1);  // in flight during this chunk's products
+            const int nt = (cl + 15) >> 4;
+            const int nst = (nt + 3) >> 2;  // strips of 4 line tiles sharing the A operand
+            double *Tb = T + (int64_t)bi * max_n * lines + l0;
+            for (int unit = wave; unit < mt * nst; unit += kFitThreads / 64) {
+                const int ti = unit / nst, tj0 = 4 * (unit - ti * nst);
+                const int k = 16 * ti + lr;
+                f64x4 acc[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    const int z = 4 * ks + lk;
+                    const bool zok = z < r2;
+                    const double av = (k < nz && zok) ? sm.X[k][z] : 0.0;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int kk = 16 * ti + 4 * r + lk, ll = 16 * (tj0 + q) + lr;
-                    if (kk < nz && ll < cl) Tb[(int64_t)kk * lines + ll] = acc[q][r];
+                    for (int q = 0; q < 4; ++q) {
+                        const int li = 16 * (tj0 + q) + lr;
+                        const double bv = (li < cl && zok) ? (double)sm.ys[li][z] : 0.0;
+                        acc[q] = mfma64(av, bv, acc[q]);  // four independent chains
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int kk = 16 * ti + 4 * r + lk, ll = 16 * (tj0 + q) + lr;
+                        if (kk < nz && ll < cl) Tb[(int64_t)kk * lines + ll] = acc[q][r];
+                    }
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -291,7 +320,58 @@ struct FitXYSmem {
 // steps 4t + r (t = the U^T tile), so U never leaves registers; the wave's
 // X_x rows are held in registers as the B operand of the first product for
 // every k of the group.  LDS holds X_y and the slice only (two workgroups
-// per CU).
+// per CU); the next k's slice is loaded into registers while the products
+// of this one run, and the second product runs over the block's j tiles
+// only (one straight-line instance per tile count).
+constexpr int kSliceRegs = kFitR * kFitR / kFitThreads;  // slice doubles per thread
+
+template <int NQ>
+__device__ __forceinline__ void fit_xy_slice(const FitXYSmem &sm, int wave, int lr, int lk,
+                                             int r0, int r1, int nx, int ny, int nz, int k,
+                                             const double (&xb)[kFitR / 4], float *Pb) {
+    constexpr int kKS = kFitR / 4;  // K steps of a 64-long contraction
+    // U^T[yy][i] for the yy tiles t: A = S^T[yy][x] = S[x][yy]
+    f64x4 u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // every K step and tile runs (entries outside the slice are selected to
+    // zero: no scalar conditions in the unrolled chains)
+#pragma unroll
+    for (int ks = 0; ks < kKS; ++ks) {
+        const int x = 4 * ks + lk;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int yy = 16 * t + lr;
+            const double sv = sm.S[x][yy];
+            u[t] = mfma64((yy < r1 && x < r0) ? sv : 0.0, xb[ks], u[t]);
+        }
+    }
+    // P[i][j] = sum_yy U[i][yy] X_y[j][yy]: A for K step 4t + r is component
+    // r of u[t] (U[16 wave + l%16][4(4t + r) + l/16]), over the NQ j tiles
+    f64x4 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int yy = 4 * (4 * t + r) + lk;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = 16 * q + lr;
+                const double xv = sm.Xy[j][yy];
+                acc[q] = mfma64(u[t][r], (j < ny && yy < r1) ? xv : 0.0, acc[q]);
+            }
+        }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 16 * wave + 4 * r + lk, jj = 16 * q + lr;
+            if (ii < nx && jj < ny) Pb[((int64_t)ii * ny + jj) * nz + k] = (float)acc[q][r];
+        }
+}
+
 __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blocks, int nblocks,
                                                              const float *knots, int r0, int r1,
                                                              int max_n, int kgroup,
@@ -302,7 +382,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     constexpr int kKS = kFitR / 4;  // K steps of a 64-long contraction
-    const int64_t lines = (int64_t)r0 * r1;
+    const int lines = r0 * r1;
     const int groups = (max_n + kgroup - 1) / kgroup;
     for (int64_t item = blockIdx.x; item < (int64_t)nblocks * groups; item += gridDim.x) {
         const int bi = (int)(item / groups);
@@ -327,54 +407,34 @@ __global__ __launch_bounds__(kFitThreads) void fit_xy_kernel(const fa_block *blo
         }
         float *Pb = ctrl + b.ctrl_off;
         const int k1 = min(nz, k0 + kgroup);
-        for (int k = k0; k < k1; ++k) {
+        const int nq = (ny + 15) >> 4;
+        // slice k in registers: element e = tid + kFitThreads m of the r0 x r1 slice
+        double sv[kSliceRegs];
+        auto fetch = [&](int k) {
             const double *Tk = T + ((int64_t)bi * max_n + k) * lines;
-            for (int e = tid; e < (int)lines; e += kFitThreads) {
-                const int x = e / r1;
-                sm.S[x][e - x * r1] = Tk[e];
+#pragma unroll
+            for (int m = 0; m < kSliceRegs; ++m) {
+                const int e = tid + kFitThreads * m;
+                sv[m] = (k < k1 && e < lines) ? Tk[e] : 0.0;
+            }
+        };
+        fetch(k0);
+        for (int k = k0; k < k1; ++k) {
+#pragma unroll
+            for (int m = 0; m < kSliceRegs; ++m) {
+                const int e = tid + kFitThreads * m;
+                if (e < lines) {
+                    const int x = e / r1;
+                    sm.S[x][e - x * r1] = sv[m];
+                }
             }
             __syncthreads();
+            fetch(k + 1);  // in flight during this slice's products
             if (rows) {
-                // U^T[yy][i] for the yy tiles t: A = S^T[yy][x] = S[x][yy]
-                f64x4 u[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) u[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-                // every K step and tile runs (entries outside the slice are
-                // selected to zero: no scalar conditions in the unrolled chains)
-#pragma unroll
-                for (int ks = 0; ks < kKS; ++ks) {
-                    const int x = 4 * ks + lk;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int yy = 16 * t + lr;
-                        const double sv = sm.S[x][yy];
-                        u[t] = mfma64((yy < r1 && x < r0) ? sv : 0.0, xb[ks], u[t]);
-                    }
-                }
-                // P[i][j] = sum_yy U[i][yy] X_y[j][yy]: A for K step 4t + r is
-                // component r of u[t] (U[16 wave + l%16][4(4t + r) + l/16])
-                f64x4 acc[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int yy = 4 * (4 * t + r) + lk;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int j = 16 * q + lr;
-                            const double xv = sm.Xy[j][yy];
-                            acc[q] = mfma64(u[t][r], (j < ny && yy < r1) ? xv : 0.0, acc[q]);
-                        }
-                    }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int ii = 16 * wave + 4 * r + lk, jj = 16 * q + lr;
-                        if (ii < nx && jj < ny) Pb[((int64_t)ii * ny + jj) * nz + k] = (float)acc[q][r];
-                    }
+                if (nq >= 4) fit_xy_slice<4>(sm, wave, lr, lk, r0, r1, nx, ny, nz, k, xb, Pb);
+                else if (nq == 3) fit_xy_slice<3>(sm, wave, lr, lk, r0, r1, nx, ny, nz, k, xb, Pb);
+                else if (nq == 2) fit_xy_slice<2>(sm, wave, lr, lk, r0, r1, nx, ny, nz, k, xb, Pb);
+                else fit_xy_slice<1>(sm, wave, lr, lk, r0, r1, nx, ny, nz, k, xb, Pb);
             }
             __syncthreads();
         }
@@ -550,9 +610,13 @@ hipError_t launch_fit_products(const fa_block *blocks, int nblocks, const float 
                                int ry, int rz, int max_n, const float *samples, double *T,
                                const double *X, int64_t xstride, float *ctrl, hipStream_t s) {
     const int64_t chunks = ((int64_t)rx * ry + kZLines - 1) / kZLines;
-    const int gz = (int)std::min<int64_t>((int64_t)nblocks * chunks, 65536);
+    // chunks per workgroup: as many as leave about 512 workgroups (two per CU)
+    const int cgroup =
+        (int)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)nblocks * chunks / 512));
+    const int64_t zitems = (int64_t)nblocks * ((chunks + cgroup - 1) / cgroup);
+    const int gz = (int)std::min<int64_t>(zitems, 65536);
     hipLaunchKernelGGL(fit_z_kernel, dim3(gz), dim3(kFitThreads), sizeof(FitZSmem), s, blocks,
-                       nblocks, knots, rx, ry, rz, max_n, samples, X, xstride, T);
+                       nblocks, knots, rx, ry, rz, max_n, cgroup, samples, X, xstride, T);
     // k values per workgroup: as many as keep about 2048 workgroups busy
     const int kgroup = (int)std::max<int64_t>(1, std::min<int64_t>(max_n, (int64_t)nblocks * max_n / 2048));
     const int64_t groups = (max_n + kgroup - 1) / kgroup;
