@@ -100,6 +100,24 @@ def timed_steps(fn, steps, warmup, stream):
     return wall * 1e3 / steps, sum(ev_ms) / len(ev_ms), min(ev_ms)
 
 
+def timed_launches(fn, reps, steps, warmup, stream):
+    """Average duration of one launch of fn when launched back to back: a
+    HIP graph of reps calls, replayed W + K times with HIP events around each
+    of the K replays (no host latency inside the timed region)."""
+    import torch
+
+    import paper_2409_00184_amd as fa
+
+    def many():
+        for _ in range(reps):
+            fn()
+
+    g, _ = fa.capture(many)
+    ms, ev_ms, mn = timed_steps(g.replay, steps, warmup, stream)
+    del g
+    return ms / reps, ev_ms / reps, mn / reps
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -910,9 +928,12 @@ def bench_c4(args):
     out = torch.empty((b.nblocks, 1) + res, device="cuda")
     gin = torch.randn_like(out)
     G = torch.empty_like(m.ctrl)
-    fms, fev, _ = timed_steps(lambda: fa.decode(m, res, 1, plan=plan, out=out), 20, 3, stream)
-    bms, bev, _ = timed_steps(lambda: fa.decode_backward(m, res, gin, 1, grad_ctrl=G), 20, 3,
-                              stream)
+    # (ten launches per replayed graph: a launch's own duration, without the
+    # host's launch latency that events around a single call would include)
+    fms, fev, _ = timed_launches(lambda: fa.decode(m, res, 1, plan=plan, out=out), 10, 10, 2,
+                                 stream)
+    bms, bev, _ = timed_launches(lambda: fa.decode_backward(m, res, gin, 1, grad_ctrl=G), 10, 10,
+                                 2, stream)
     nvox = b.nblocks * 64 ** 3
     lat = 4 * int(sum(int(n.prod()) for n in b.ncp))
     # loss and gradient of the fitted lattice against the FP64 oracle:
