@@ -891,9 +891,10 @@ def bench_c4(args):
     plan = fa.Plan(m, res)
     yt = torch.as_tensor(y, device="cuda").reshape(b.nblocks, 1, *res)
     ctrl = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
-    # one fused Adam kernel per step; gradients are set, not accumulated into
-    # a zeroed buffer (the adjoint writes every control point)
-    opt = torch.optim.Adam([ctrl], lr=0.05, fused=True)
+    # the library's Adam step (fa_adam_step: a counter launch and one update
+    # launch); gradients are set, not accumulated into a zeroed buffer (the
+    # adjoint writes every control point)
+    opt = fa.Adam([ctrl], lr=0.05)
     losses = []
 
     yf = yt.reshape(b.nblocks, *res).contiguous()
@@ -916,11 +917,11 @@ def bench_c4(args):
     ms, ev_ms, _ = timed_steps(lambda: losses.append(it()), args.steps, args.warmup, stream)
     first, last = float(losses[0].detach()), float(losses[-1].detach())
     ms_t = timed_steps(it_torch, args.steps, args.warmup, stream)[0]
-    # the same iteration captured into one HIP graph (the same fused Adam,
-    # capturable); every replay does the whole iteration's work
+    # the same iteration captured into one HIP graph (the same Adam step,
+    # its step count on the device); every replay does the whole iteration's work
     mg = fa.MicroModels.from_batch(b)
     ctrl_g = torch.zeros(b.ctrl.size, device="cuda", requires_grad=True)
-    opt_g = torch.optim.Adam([ctrl_g], lr=0.05, fused=True, capturable=True)
+    opt_g = fa.Adam([ctrl_g], lr=0.05)
     graph, loss_g = fa.capture_fit_step(ctrl_g, opt_g, mg, res, yf, fa.Plan(mg, res))
     ms_g = timed_steps(graph.replay, args.steps, args.warmup, stream)[0]
     loss_graph = float(loss_g)

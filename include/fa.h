@@ -304,6 +304,31 @@ fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const floa
                              float *grad_ctrl, void *stream);
 
 /*
+ * One Adam step (Kingma and Ba, 2015) on the control points of a
+ * gradient-based fit: the least-squares fit of a lattice to its block's
+ * samples that Alg. 1's model(NCP, degree) step (Sec. 4.2.1) solves, whose
+ * gradient fa_decode_backward gives.  In place, over n FP32 values, in the
+ * form PyTorch's Adam uses (no amsgrad):
+ *   g = grad + weight_decay * param
+ *   exp_avg    = exp_avg + (1 - beta1) (g - exp_avg)
+ *   exp_avg_sq = beta2 exp_avg_sq + (1 - beta2) g^2
+ *   param     -= lr / (1 - beta1^t) * exp_avg / (sqrt(exp_avg_sq) / sqrt(1 - beta2^t) + eps)
+ *   param, exp_avg, exp_avg_sq  device FP32 [n], updated in place
+ *   grad                        device FP32 [n]
+ *   state      device FP32 [3], caller-owned, zero before the first step:
+ *              {t, 1 - beta1^t, sqrt(1 - beta2^t)}; every call first
+ *              advances t by one on the device, so a captured graph steps
+ *              correctly on every replay
+ * With n = 0 only the step count advances (the arrays may be null).
+ * Errors: FA_ERR_INVALID_ARG for a null state, null arrays with n > 0,
+ * n < 0, beta1 or beta2 outside [0, 1), eps <= 0 and non-finite lr, eps or
+ * weight_decay.
+ */
+fa_status fa_adam_step(float *param, const float *grad, float *exp_avg, float *exp_avg_sq,
+                       int64_t n, float lr, float beta1, float beta2, float eps,
+                       float weight_decay, float *state, void *stream);
+
+/*
  * Per-block max-abs scaling and rounding to BF16/FP16 (row a4): for each
  * block, s_b = max |P_b| (1 when the lattice is all zeros), blocks[b].scale
  * = s_b, and ctrl_lp = round-to-nearest-even(P_b / s_b).

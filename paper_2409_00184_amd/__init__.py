@@ -8,9 +8,9 @@ the binding raises.
 Entry points (same names as the C ABI):
   fa_validate_blocks, fa_plan_decode, fa_decode_blocks,
   fa_decode_blocks_plain, fa_query_points, fa_query_rays, fa_decode_backward,
-  fa_quantize_blocks
+  fa_quantize_blocks, fa_adam_step
 and the conveniences MicroModels, Plan, decode, decode_plain, query, query_rays,
-decode_backward, FADecode (torch.autograd.Function), capture.
+decode_backward, FADecode (torch.autograd.Function), Adam, capture.
 """
 import ctypes
 import os
@@ -102,6 +102,9 @@ def _load():
     L.fa_render_rays.restype = ctypes.c_int
     L.fa_render_rays.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, i32, i32,
                                  vp, vp, vp, vp]
+    L.fa_adam_step.restype = ctypes.c_int
+    L.fa_adam_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp]
     L.fa_mse_grad.restype = ctypes.c_int
     L.fa_mse_grad.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, vp]
     L.fa_decode_residual_workspace.restype = i64
@@ -374,6 +377,42 @@ def decode_backward(models, res, grad_out, mask=1, grad_ctrl=None, stream=None):
                                 _stream(stream))
     _check("fa_decode_backward", st)
     return grad_ctrl
+
+
+class Adam(torch.optim.Optimizer):
+    """Adam on FP32 CUDA parameters, one fa_adam_step per parameter tensor
+    (two HIP launches: the device step counter, then the update).  Same
+    update as torch.optim.Adam (no amsgrad, weight decay added to the
+    gradient); the step count is kept on the device, so the step can be
+    captured into a HIP graph (capture_fit_step) once one eager step has
+    created the state."""
+
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0):
+        super().__init__(params, dict(lr=lr, betas=betas, eps=eps, weight_decay=weight_decay))
+
+    @torch.no_grad()
+    def step(self, closure=None):
+        loss = None
+        if closure is not None:
+            with torch.enable_grad():
+                loss = closure()
+        for group in self.param_groups:
+            b1, b2 = group["betas"]
+            for p in group["params"]:
+                if p.grad is None:
+                    continue
+                assert p.dtype == torch.float32 and p.is_cuda and p.is_contiguous()
+                g = p.grad if p.grad.is_contiguous() else p.grad.contiguous()
+                st = self.state[p]
+                if not st:
+                    st["exp_avg"] = torch.zeros_like(p)
+                    st["exp_avg_sq"] = torch.zeros_like(p)
+                    st["state"] = torch.zeros(3, dtype=torch.float32, device=p.device)
+                _check("fa_adam_step", lib.fa_adam_step(
+                    _ptr(p), _ptr(g), _ptr(st["exp_avg"]), _ptr(st["exp_avg_sq"]), p.numel(),
+                    float(group["lr"]), float(b1), float(b2), float(group["eps"]),
+                    float(group["weight_decay"]), _ptr(st["state"]), _stream()))
+        return loss
 
 
 # ------------------------------------------------------- adaptive encoding

@@ -512,6 +512,19 @@ fa_status fa_decode_backward(const fa_block *blocks, int32_t nblocks, const floa
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
+fa_status fa_adam_step(float *param, const float *grad, float *exp_avg, float *exp_avg_sq,
+                       int64_t n, float lr, float beta1, float beta2, float eps,
+                       float weight_decay, float *state, void *stream) {
+    if ((n > 0 && (!param || !grad || !exp_avg || !exp_avg_sq)) || !state || n < 0 ||
+        !std::isfinite(lr) ||
+        !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f) || !std::isfinite(eps) || !std::isfinite(weight_decay))
+        return FA_ERR_INVALID_ARG;
+    hipError_t e = launch_adam(param, grad, exp_avg, exp_avg_sq, n, lr, beta1, beta2, eps,
+                               weight_decay, state, (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctrl_f32,
                              fa_dtype dtype, void *ctrl_lp, void *stream) {
     if (!blocks || nblocks <= 0 || !ctrl_f32 || !ctrl_lp) return FA_ERR_INVALID_ARG;

@@ -220,6 +220,16 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     assert L.fa_decode_backward(vp, 1, vp, fa._i32x3((64, 65, 64)), 1, vp, vp, None) == 2
     assert L.fa_decode_backward(vp, 1, vp, r, 16, vp, vp, None) == 1
     assert L.fa_quantize_blocks(vp, 1, vp, 0, vp, None) == 1
+    # Adam step: every argument error returns before the device is touched
+    ok = dict(lr=0.05, b1=0.9, b2=0.999, eps=1e-8, wd=0.0)
+    adam = lambda p, n, **kw: L.fa_adam_step(p, vp, vp, vp, n, kw["lr"], kw["b1"], kw["b2"],
+                                             kw["eps"], kw["wd"], vp, None)
+    assert adam(None, 8, **ok) == 1
+    assert L.fa_adam_step(vp, vp, vp, vp, 8, 0.05, 0.9, 0.999, 1e-8, 0.0, None, None) == 1
+    assert adam(vp, -1, **ok) == 1
+    for k, v in (("b1", 1.0), ("b1", -0.1), ("b2", 1.0), ("eps", 0.0), ("eps", float("inf")),
+                 ("lr", float("nan")), ("wd", float("inf"))):
+        assert adam(vp, 8, **dict(ok, **{k: v})) == 1, (k, v)
     # the allocation-free residual: bad arguments, then a batch whose work
     # items exceed its fixed scratch array, both before any device call
     assert L.fa_decode_residual_noalloc(None, 1, vp, vp, r, None, None, None, 0, vp, 1.0, vp,

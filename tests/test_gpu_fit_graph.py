@@ -220,7 +220,7 @@ def test_graph_replay_matches_eager(fa):
         _ = (out * 2).sum().item()  # eager work between replays
 
 
-@pytest.mark.parametrize("adam", ["capturable", "fused"])
+@pytest.mark.parametrize("adam", ["capturable", "fused", "native"])
 def test_captured_fit_step_matches_eager(fa, adam):
     """A whole fit iteration (decode, fused MSE, adjoint, capturable Adam:
     multi-kernel or fused) captured into one graph: every replay, with eager
@@ -237,7 +237,10 @@ def test_captured_fit_step_matches_eager(fa, adam):
     for _ in range(2):
         m = models(b)
         ctrl = P0.clone().requires_grad_(True)
-        opt = torch.optim.Adam([ctrl], lr=0.05, capturable=True, fused=(adam == "fused"))
+        if adam == "native":
+            opt = fa.Adam([ctrl], lr=0.05)
+        else:
+            opt = torch.optim.Adam([ctrl], lr=0.05, capturable=True, fused=(adam == "fused"))
         runs.append((m, ctrl, opt, fa.Plan(m, res)))
     me, ce, oe, pe = runs[0]
     mg, cg, og, pg = runs[1]
@@ -301,3 +304,39 @@ def test_autotune_interleaved_layout(fa, tmp_path, monkeypatch):
     assert a.shape == (b.nblocks,) + res + (4,)
     assert torch.equal(a, fa.decode(m, res, mk))
     assert torch.equal(a, fa.decode(m, res, 15).permute(0, 2, 3, 4, 1))
+
+
+@pytest.mark.parametrize("n,offset,wd", [(4096 * 5 + 12, 0, 0.0), (4099, 0, 0.01), (1000, 1, 0.0),
+                                         (3, 0, 0.0), (0, 0, 0.0)])
+def test_native_adam_matches_torch(fa, n, offset, wd):
+    """fa.Adam (fa_adam_step) against torch.optim.Adam on the same FP32
+    parameters and gradients for K steps: 16-byte and 4-byte aligned arrays,
+    lengths with a ragged tail, weight decay, an empty tensor.  Bound: each
+    step rounds about ten FP32 operations per element, and the two sides
+    compute 1 - b^t differently (FP32 pow here, FP64 there), so after K steps
+    |p - p_torch| <= 32 K u32 (max |p| + lr)."""
+    say("native adam", n, offset, wd)
+    g = torch.Generator().manual_seed(71 + n)
+    K, lr = 10, 0.05
+    base = torch.randn(n + offset, generator=g)
+    grads = [torch.randn(n, generator=g) for _ in range(K)]
+    pa = base.cuda()[offset:] if offset else base.cuda()
+    pa = torch.nn.Parameter(pa) if offset == 0 else pa.requires_grad_(True)
+    pt = torch.nn.Parameter(base[offset:].clone().cuda())
+    oa = fa.Adam([pa], lr=lr, betas=(0.9, 0.99), eps=1e-8, weight_decay=wd)
+    ot = torch.optim.Adam([pt], lr=lr, betas=(0.9, 0.99), eps=1e-8, weight_decay=wd,
+                          foreach=False)
+    for k in range(K):
+        pa.grad = grads[k].cuda()
+        pt.grad = grads[k].cuda()
+        oa.step()
+        ot.step()
+    torch.cuda.synchronize()
+    if n == 0:
+        return
+    d = (pa.detach() - pt.detach()).abs().max().item()
+    lim = 32 * K * 2.0 ** -24 * (pt.detach().abs().max().item() + lr)
+    say("  max |diff|", d, "bound", lim)
+    assert d <= lim
+    st = oa.state[pa]["state"].cpu().numpy()
+    assert st[0] == K
