@@ -552,6 +552,18 @@ def bench_f1(args):
     scale = np.abs(ref).max(0)
     err = {k: float(np.abs(got[:, c] - ref[:, c]).max() / scale[c])
            for c, k in enumerate(["R", "G", "B", "A"])}
+    # the same view of the micro-models with every interior knot jittered
+    # (span search by bisection with cross-lane knot reads in block-uniform
+    # waves, per lane otherwise)
+    bn = fi.config_c3_blocks(nonuniform=True)
+    mn = fa.MicroModels.from_batch(bn)
+    rnu = lambda: fa.render(mn, rays, W, H, tf, (16, 16, 16), (0, 0, 0), (1, 1, 1), boc, S,
+                            opacity_max=2.0, tf_range=(-4.0, 4.0), out=img, **shade)
+    graph, _ = fa.capture(rnu)
+    ms_n, ev_n, _ = timed_steps(graph.replay, args.steps, args.warmup, stream)
+    del graph, mn
+    run(2.0)()
+    torch.cuda.synchronize()
     flops = 2 * 192 + 3 * 45 + 40  # contraction + basis/span + TF/shading/compositing
     tflops = n * flops / (ev_ms * 1e-3) / 1e12
     line = _common(args, "rendered samples/sec (DVR ray casting)", n / (ms * 1e-3), "samples/s",
@@ -568,6 +580,8 @@ def bench_f1(args):
                     "frames_per_s": 1e3 / ms,
                     "early_termination": {"opacity_max": 0.98, "ms_per_step": ms_t,
                                           "avg_launch_ms": ev_t, "frames_per_s": 1e3 / ms_t},
+                    "nonuniform_knots": {"ms_per_step": ms_n, "avg_launch_ms": ev_n,
+                                         "vs_uniform": ms / ms_n},
                     "err_vs_fp64": err})
     if not args.no_cpu_baseline:
         th = oracle.nthreads_default()

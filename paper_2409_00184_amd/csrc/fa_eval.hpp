@@ -78,6 +78,7 @@ struct BlockLoads;
 template <>
 struct BlockLoads<true> {
     static constexpr bool kRowPointers = false;
+    static constexpr bool kWaveKnots = true;  // every lane in one micro-model
     __amdgpu_buffer_rsrc_t kr, cr;
     // the lattice resource ends on a dword boundary: with 2-byte values and
     // an odd count the last value shares its dword with the next two bytes,
@@ -88,6 +89,43 @@ struct BlockLoads<true> {
     template <int N>
     __device__ __forceinline__ Vec<N> knots(uint32_t i, uint32_t u) const {
         return bload<N>(kr, i * 4u, u * 4u);
+    }
+    // Span and knot window of a non-uniform axis (knots from element k0):
+    // every lane of the wave is in this micro-model, so the wave reads the
+    // axis's knots once, lane j holding t[j] (and t[64 + j]), and each lane
+    // runs its binary search and gathers its window with cross-lane reads
+    // (ds_bpermute) instead of dependent memory loads.  Same span and
+    // window values as span_search and a knot load.
+    template <int P>
+    __device__ __forceinline__ int span_window(uint32_t k0, int n, float u,
+                                               float (&tw)[2 * P]) const {
+        const int lane = (int)__lane_id(), nk = n + P + 1;
+        const float ka = bload<1>(kr, (uint32_t)min(lane, nk - 1) * 4u, k0 * 4u).v[0];
+        const bool two = nk > kWave;  // uniform
+        const float kb =
+            two ? bload<1>(kr, (uint32_t)min(kWave + lane, nk - 1) * 4u, k0 * 4u).v[0] : 0.0f;
+        auto kn = [&](int j) {
+            const float a = __shfl(ka, j & (kWave - 1));
+            if (!two) return a;
+            const float b = __shfl(kb, j & (kWave - 1));
+            return j < kWave ? a : b;
+        };
+        // every lane takes part in every cross-lane read (no divergent
+        // branch around them): largest s in [P, n-1] with t[s] <= u, by
+        // bisection keeping t[lo] <= u < t[hi]; u >= t[n] gives n-1
+        const bool top = u >= kn(n);
+        int lo = P, hi = n;
+        while (__any(hi - lo > 1)) {
+            const int mid = (lo + hi) >> 1;
+            const float tm = kn(mid);
+            const bool act = hi - lo > 1, below = u < tm;
+            hi = act && below ? mid : hi;
+            lo = act && !below ? mid : lo;
+        }
+        const int s = top ? n - 1 : lo;
+#pragma unroll
+        for (int m = 0; m < 2 * P; ++m) tw[m] = kn(s - P + 1 + m);
+        return s;
     }
     template <int N>
     __device__ __forceinline__ Vec<N> rowf(uint32_t i, uint32_t u) const {
@@ -110,6 +148,7 @@ struct BlockLoads<true> {
 template <>
 struct BlockLoads<false> {
     static constexpr bool kRowPointers = false;
+    static constexpr bool kWaveKnots = false;
     const float *kp;
     const char *cp;
     __device__ BlockLoads(const float *knots, uint32_t, const void *ctrl, uint32_t)
@@ -167,6 +206,7 @@ __device__ __forceinline__ int axis_window(const LD &L, uint32_t k0, int n,
         for (int m = 0; m < 2 * P; ++m) tw[m] = w.v[m];
         return s0 + d;
     }
+    if constexpr (LD::kWaveKnots) return L.template span_window<P>(k0, n, u, tw);
     const int s = span_search(n, P, t, u);
     const Vec<2 * P> w = L.template knots<2 * P>((uint32_t)(s - P + 1), k0);
 #pragma unroll
@@ -336,8 +376,11 @@ __device__ __forceinline__ float4 eval_point(const QueryLaunch &a, float x, floa
     int blk = live ? a.block_of_cell[(bx * a.nb[1] + by) * a.nb[2] + bz] : -1;
     if (blk >= a.nblocks) blk = -1;  // anything outside [0, nblocks) is an empty cell
     float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const int blk0 = __builtin_amdgcn_readfirstlane(blk);
-    if (__all(blk == blk0)) {
+    // the micro-model of the first live lane; lanes that are not live take
+    // part in its evaluation and their results are discarded by the caller
+    const uint64_t lv = __ballot(live);
+    const int blk0 = lv ? __builtin_amdgcn_readlane(blk, (int)__builtin_ctzll(lv)) : -1;
+    if (__all(!live || blk == blk0)) {
         if (blk0 >= 0) {
             const fa_block &B = a.blocks[blk0];
             r = query_any<DT, true>(a, uniform_view_of(B), uni(B.degree[0]), uu);

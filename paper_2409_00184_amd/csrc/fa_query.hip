@@ -94,6 +94,7 @@ struct RaySmem {
 // Knot windows and lattice rows of a micro-model held in an LDS slot.
 struct LdsLoads {
     static constexpr bool kRowPointers = true;
+    static constexpr bool kWaveKnots = false;
     const float *kn;
     const uint32_t *lat;
     __device__ __forceinline__ const float *row_base(uint32_t o0) const {
