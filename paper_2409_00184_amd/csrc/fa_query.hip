@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
 #define FA_SLOT_WORDS 18432
 #endif
 constexpr int kLW = FA_RAYS_WAVES;       // waves per workgroup = rows of rays
-constexpr int kLR = 8;                   // rays per wave (one row of pixels)
+constexpr int kLR = 16;                  // rays per wave (one row of pixels)
 constexpr int kLS = kWave / kLR;         // samples per ray and step
 constexpr int kSlotWords = FA_SLOT_WORDS;  // lattice words (4 bytes) per slot
 constexpr int kSlotKnots = 3 * (FA_MAX_NCP + FA_MAX_DEGREE + 1);

@@ -35,9 +35,10 @@ def test_traffic_files_match_sources(kernel, workload):
     assert bench.traffic_from_profiles(kernel, workload) == t["hbm_bytes_per_launch"]
     # the counters see at least the algorithmic bytes (the render re-fetches
     # lattice lines, the ray-ordered query copies each micro-model a ray tile
-    # enters into LDS; the others stay within 20%)
+    # enters into LDS: about one copy per tile and micro-model, from L2 and
+    # the Infinity Cache; the others stay within 20%)
     ratio = t["hbm_bytes_per_launch"] / t["alg_bytes_per_launch"]
-    assert 0.99 < ratio < {"render": 5.0, "query": 1.5}.get(kernel, 1.2)
+    assert 0.99 < ratio < {"render": 5.0, "query": 2.0}.get(kernel, 1.2)
 
 
 def test_stale_traffic_summary_reports_null(tmp_path):
