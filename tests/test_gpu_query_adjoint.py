@@ -116,8 +116,8 @@ def test_query_rays_low_precision_and_nonuniform(fa, dtype):
     """The ray order on 2-byte lattices (rows read from the LDS slots as
     dword pairs) and on blocks with non-uniform knots (binary span search on
     the knots in LDS), including blocks larger than one LDS slot (the
-    per-lane fallback): bit for bit the flat query, which the oracle
-    checks."""
+    per-lane fallback) in every lattice type: bit for bit the flat query,
+    which the oracle checks."""
     say("query rays lowp / nonuniform", dtype)
     g = fi.rng(47)
     nb = (4, 4, 4)
@@ -126,7 +126,9 @@ def test_query_rays_low_precision_and_nonuniform(fa, dtype):
         p = int(g.choice([2, 3]))
         n = [int(v) for v in g.integers(p + 1, 33, 3)]
         if k == 5:
-            n = [40, 30, 20]  # 24000 lattice values: above one LDS slot in FP32
+            n = [40, 30, 20]  # 24000 values: above one LDS slot in FP32
+        if k == 9:
+            n = [64, 40, 20]  # 51200 values: above one LDS slot in 2 bytes too
         ks = []
         for a in range(3):
             if k % 3 == 0 and n[a] > p + 1:
