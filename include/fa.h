@@ -218,9 +218,10 @@ fa_status fa_query_points(const fa_block *blocks, int32_t nblocks,
  * [height][width][samples][3] (ray-major, row-major pixels), out =
  * [height][width][samples][4].  Results are identical to fa_query_points
  * on the flattened arrays; only the order in which the GPU visits the
- * samples differs (a workgroup walks a 2 x 4 tile of adjacent rays in
- * lockstep, one ray per wave, so its waves share micro-models and knot
- * spans at every step).
+ * samples differs: a workgroup marches a 16 x 16 tile of adjacent rays in
+ * lockstep (a wave: one row of 16 rays, 4 consecutive samples of each per
+ * step), and copies the one or two micro-models its rays are in at each
+ * step into LDS, where the evaluation reads them.
  * Errors: FA_ERR_INVALID_ARG for width, height or samples <= 0, and as
  * fa_query_points.
  */

@@ -274,7 +274,7 @@ def test_query_lattice_beyond_4gb(fa, dtype):
     """Blocks whose lattice lies past the first 4 GB of the lattice array
     (element offsets beyond 32-bit byte range) give bit for bit the values
     of the same blocks near its start, for points spread over several
-    blocks per wave."""
+    blocks per wave, in the flat and the ray order."""
     import copy
     say("query far lattice", dtype)
     nb = (2, 2, 2)
@@ -297,5 +297,10 @@ def test_query_lattice_beyond_4gb(fa, dtype):
     rn = fa.query(near, xyz, nb, o, e, bocd, dtype=dtype)
     rf = fa.query(far, xyz, nb, o, e, bocd, dtype=dtype)
     assert torch.equal(rn, rf)
+    # the ray order on the same positions (50 x 40 rays x 100 samples):
+    # waves with samples outside the LDS slots read the far blocks one block
+    # at a time (FP32: past 4 GB) or through 32-bit offsets (2-byte lattices)
+    rr = fa.query_rays(far, xyz, 50, 40, 100, nb, o, e, bocd, dtype=dtype)
+    assert torch.equal(rn, rr)
     del big, far
     torch.cuda.empty_cache()
