@@ -35,8 +35,6 @@
 // decode_plain: the baseline -- one thread per voxel, one launch per block,
 //   each thread doing its own span searches, basis evaluation and (p+1)^3
 //   window sum straight from global memory.
-#include <type_traits>
-
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -137,17 +135,34 @@ __device__ void sep_item(const DecodeLaunch &a, int b, int row0, int nrows, int 
     basis_ders<P>(tz, sz, zw, zB, zD);
     const int kz0 = sz - P;
 
-    // e / plane as a multiply-shift: exact for e < 2^16 and plane < 2^14
-    // (the slab holds at most kSlabMax < 2^16 floats and plane <= 64*64)
-    const uint64_t recip = ((1ull << 30) + plane - 1) / plane;
+    // Slab element e = ii * plane + r is value r of control plane c0 + ii's
+    // rows jlo..jhi, which lie back to back in the lattice.  A thread walks
+    // its elements (stride nthr) with (ii, r) kept incrementally, and issues
+    // four loads before their four LDS writes.
+    const int nynz = ny * nz;
+    const int dii = nthr / plane, dr = nthr - dii * plane;
+    const int ii0 = tid / plane, r0 = tid - ii0 * plane;
     auto stage = [&](int c0, int c1) {
         const int cnt = (c1 - c0) * plane;
-#pragma unroll 4
-        for (int e = tid; e < cnt; e += nthr) {
-            const int ii = (int)(((uint64_t)(uint32_t)e * recip) >> 30);
-            const int r = e - ii * plane;
-            const int64_t gi = coff + (int64_t)((c0 + ii) * ny + jlo) * nz + r;
-            sm.slab[e] = load_ctrl(a.ctrl, a.dtype, gi, scale);
+        const int64_t base = coff + (int64_t)(c0 * ny + jlo) * nz;
+        int ii = ii0, r = r0;
+        for (int e0 = tid; e0 < cnt; e0 += 4 * nthr) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q] = e0 + q * nthr < cnt
+                           ? load_ctrl(a.ctrl, a.dtype, base + (ii * nynz + r), scale)
+                           : 0.0f;
+                r += dr;
+                ii += dii;
+                if (r >= plane) {
+                    r -= plane;
+                    ++ii;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (e0 + q * nthr < cnt) sm.slab[e0 + q * nthr] = v[q];
         }
     };
 
