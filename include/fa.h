@@ -403,6 +403,20 @@ fa_status fa_mse_grad(const float *decoded, const float *samples, int32_t nblock
                       float grad_scale, float *grad, double *sumsq, void *stream);
 
 /*
+ * The loss of a fit from the per-block sums of squares of fa_mse_grad or
+ * fa_decode_residual (Alg. 1's model fit minimises it):
+ *   loss[0] = (float)(sum_b sumsq[b] / count),
+ * with count the number of residuals (all voxels of all blocks).  The FP64
+ * sum runs in a fixed order (each of 256 threads adds every 256th block in
+ * order, then a binary tree over the threads), one launch.
+ *   sumsq  device FP64 [nblocks];  loss  device FP32 [1]
+ * FA_ERR_INVALID_ARG for null pointers, nblocks <= 0 or count not positive
+ * and finite.
+ */
+fa_status fa_mse_loss(const double *sumsq, int32_t nblocks, double count, float *loss,
+                      void *stream);
+
+/*
  * The value decode of fa_decode_blocks fused with fa_mse_grad: for every
  * block b and voxel v, with f the value decode (mask 1) of the FP32 lattice,
  *   grad[b][v] = grad_scale * (f[b][v] - samples[b][v]),

@@ -8,7 +8,7 @@ the binding raises.
 Entry points (same names as the C ABI):
   fa_validate_blocks, fa_plan_decode, fa_decode_blocks,
   fa_decode_blocks_plain, fa_query_points, fa_query_rays, fa_decode_backward,
-  fa_quantize_blocks, fa_adam_step
+  fa_quantize_blocks, fa_adam_step, fa_mse_loss
 and the conveniences MicroModels, Plan, decode, decode_plain, query, query_rays,
 decode_backward, FADecode (torch.autograd.Function), Adam, capture.
 """
@@ -20,7 +20,7 @@ import torch
 
 __all__ = ["FA_F32", "FA_BF16", "FA_F16", "BLOCK_DTYPE", "WORK_DTYPE", "FAError", "lib",
            "MicroModels", "Plan", "decode", "decode_plain", "query", "query_rays",
-           "decode_backward",
+           "decode_backward", "mse_loss",
            "FADecode", "capture", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -105,6 +105,8 @@ def _load():
     L.fa_adam_step.restype = ctypes.c_int
     L.fa_adam_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp]
+    L.fa_mse_loss.restype = ctypes.c_int
+    L.fa_mse_loss.argtypes = [vp, i32, ctypes.c_double, vp, vp]
     L.fa_mse_grad.restype = ctypes.c_int
     L.fa_mse_grad.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, vp]
     L.fa_decode_residual_workspace.restype = i64
@@ -762,11 +764,25 @@ def decode_residual_noalloc(models, res, samples, grad_scale, plan=None, tune=No
     return grad, sumsq
 
 
+def mse_loss(sumsq, count, loss=None, stream=None):
+    """(float32 scalar) sum(sumsq) / count in one launch (fa_mse_loss)."""
+    assert sumsq.dtype == torch.float64 and sumsq.is_contiguous()
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=sumsq.device)
+    _check("fa_mse_loss", lib.fa_mse_loss(_ptr(sumsq), sumsq.numel(), float(count), _ptr(loss),
+                                          _stream(stream)))
+    return loss
+
+
 class FAFitMSE(torch.autograd.Function):
     """Loss = mean over all voxels of (B(ctrl) - y)^2 in two HIP passes: the
     value decode fused with the residual, loss and cotangent
-    (fa_decode_residual; the decoded values are never stored), and in
-    backward the adjoint B^T of the cotangent.  y: [nblocks, *res] float32."""
+    (fa_decode_residual; the decoded values are never stored) and the loss
+    from its per-block sums (fa_mse_loss), and in backward the adjoint B^T of
+    the cotangent.  y: [nblocks, *res] float32.  The adjoint writes into a
+    buffer kept on `models` (zeroed once: the padding between blocks'
+    lattices, which the adjoint leaves alone, stays zero); the gradient
+    returned is a new tensor, its product with the incoming gradient."""
 
     @staticmethod
     def forward(ctx, ctrl, models, res, y, plan):
@@ -776,12 +792,17 @@ class FAFitMSE(torch.autograd.Function):
         g, sumsq = decode_residual(models, res, y, 2.0 / m_all, plan=plan)
         ctx.models, ctx.res = models, res
         ctx.save_for_backward(g)  # the cotangent 2 (f - y) / M
-        return (sumsq.sum() / m_all).to(torch.float32)
+        return mse_loss(sumsq, m_all)
 
     @staticmethod
     def backward(ctx, gl):
         (g,) = ctx.saved_tensors
-        gc = decode_backward(ctx.models, ctx.res, g, 1)
+        m = ctx.models
+        buf = getattr(m, "_adjoint_buf", None)
+        if buf is None or buf.numel() != m.ctrl.numel() or buf.device != m.ctrl.device:
+            buf = torch.zeros_like(m.ctrl)
+            m._adjoint_buf = buf
+        gc = decode_backward(m, ctx.res, g, 1, grad_ctrl=buf)
         return gc * gl, None, None, None, None
 
 

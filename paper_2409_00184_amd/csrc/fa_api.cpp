@@ -525,6 +525,14 @@ fa_status fa_adam_step(float *param, const float *grad, float *exp_avg, float *e
     return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
 }
 
+fa_status fa_mse_loss(const double *sumsq, int32_t nblocks, double count, float *loss,
+                      void *stream) {
+    if (!sumsq || !loss || nblocks <= 0 || !(count > 0.0) || !std::isfinite(count))
+        return FA_ERR_INVALID_ARG;
+    hipError_t e = launch_mse_loss(sumsq, nblocks, count, loss, (hipStream_t)stream);
+    return e == hipSuccess ? FA_OK : FA_ERR_DEVICE;
+}
+
 fa_status fa_quantize_blocks(fa_block *blocks, int32_t nblocks, const float *ctrl_f32,
                              fa_dtype dtype, void *ctrl_lp, void *stream) {
     if (!blocks || nblocks <= 0 || !ctrl_f32 || !ctrl_lp) return FA_ERR_INVALID_ARG;

@@ -136,6 +136,10 @@ hipError_t launch_stage_gather(const StageEntry *table, int n, const float *slot
 hipError_t launch_quantize(fa_block *blocks, int nblocks, const float *ctrl, int dtype,
                            void *out, hipStream_t s);
 
+// loss[0] = (float)(sum of sumsq[0..nblocks) / count), fixed order
+hipError_t launch_mse_loss(const double *sumsq, int nblocks, double count, float *loss,
+                           hipStream_t s);
+
 // one Adam step (state: device float[3] = {t, 1 - b1^t, sqrt(1 - b2^t)}, advanced first)
 hipError_t launch_adam(float *param, const float *grad, float *exp_avg, float *exp_avg_sq,
                        int64_t n, float lr, float beta1, float beta2, float eps, float wd,

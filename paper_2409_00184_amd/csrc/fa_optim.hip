@@ -9,6 +9,8 @@
 // a captured graph advances it on every replay: a one-thread kernel moves t
 // to t + 1 and stores the two bias corrections, then the update kernel
 // streams the arrays once (16-byte accesses when every array is aligned).
+// The fit's loss, the mean of the squared residuals, comes from the
+// per-block FP64 sums of squares in one single-workgroup launch.
 #include "fa_device.hpp"
 #include "fa_internal.hpp"
 
@@ -70,7 +72,30 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
     }
 }
 
+// loss[0] = (float)(sum_b sumsq[b] / count): thread t adds blocks t, t + 256,
+// ... in order, then the threads' sums meet in a fixed binary tree, so the
+// result does not depend on timing.
+__global__ __launch_bounds__(256) void mse_loss_kernel(const double *sumsq, int n, double count,
+                                                       float *loss) {
+    __shared__ double part[256];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256) t += sumsq[b];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = (float)(part[0] / count);
+}
+
 }  // namespace
+
+hipError_t launch_mse_loss(const double *sumsq, int nblocks, double count, float *loss,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(mse_loss_kernel, dim3(1), dim3(256), 0, s, sumsq, nblocks, count, loss);
+    return hipGetLastError();
+}
 
 hipError_t launch_adam(float *param, const float *grad, float *exp_avg, float *exp_avg_sq,
                        int64_t n, float lr, float beta1, float beta2, float eps, float wd,

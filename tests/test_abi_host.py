@@ -230,6 +230,13 @@ def test_hot_calls_reject_bad_arguments_without_launch(fa):
     for k, v in (("b1", 1.0), ("b1", -0.1), ("b2", 1.0), ("eps", 0.0), ("eps", float("inf")),
                  ("lr", float("nan")), ("wd", float("inf"))):
         assert adam(vp, 8, **dict(ok, **{k: v})) == 1, (k, v)
+    # the loss from per-block sums: null pointers, no blocks, a count that is
+    # not positive and finite
+    assert L.fa_mse_loss(None, 4, 8.0, vp, None) == 1
+    assert L.fa_mse_loss(vp, 4, 8.0, None, None) == 1
+    assert L.fa_mse_loss(vp, 0, 8.0, vp, None) == 1
+    for c in (0.0, -1.0, float("inf"), float("nan")):
+        assert L.fa_mse_loss(vp, 4, c, vp, None) == 1, c
     # the allocation-free residual: bad arguments, then a batch whose work
     # items exceed its fixed scratch array, both before any device call
     assert L.fa_decode_residual_noalloc(None, 1, vp, vp, r, None, None, None, 0, vp, 1.0, vp,

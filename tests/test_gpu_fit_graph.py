@@ -1,5 +1,7 @@
 """Fitting control points through torch.autograd (C4), graph capture and the
 autotuner."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -304,6 +306,32 @@ def test_autotune_interleaved_layout(fa, tmp_path, monkeypatch):
     assert a.shape == (b.nblocks,) + res + (4,)
     assert torch.equal(a, fa.decode(m, res, mk))
     assert torch.equal(a, fa.decode(m, res, 15).permute(0, 2, 3, 4, 1))
+
+
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 5000])
+def test_mse_loss_fixed_order(fa, n):
+    """fa_mse_loss against the same FP64 additions done in numpy in the
+    documented order (thread t adds blocks t, t + 256, ... in turn, then a
+    binary tree over the 256 threads): bit for bit, and within one FP32 ulp
+    of the plain sequential sum."""
+    say("mse loss", n)
+    g = np.random.Generator(np.random.PCG64(400 + n))
+    ss = g.exponential(3.0, n) * 10.0 ** g.integers(-3, 4, n)
+    count = float(n * 4096 + 7)
+    got = fa.mse_loss(torch.as_tensor(ss, device="cuda"), count).item()
+    part = np.zeros(256)
+    for t in range(256):
+        acc = 0.0
+        for b in range(t, n, 256):
+            acc = acc + ss[b]
+        part[t] = acc
+    h = 128
+    while h:
+        part[:h] = part[:h] + part[h:2 * h]
+        h //= 2
+    assert got == float(np.float32(part[0] / count))
+    seq = float(np.float32(math.fsum(ss) / count))
+    assert abs(got - seq) <= float(np.spacing(np.float32(seq)))
 
 
 @pytest.mark.parametrize("n,offset,wd", [(4096 * 5 + 12, 0, 0.0), (4099, 0, 0.01), (1000, 1, 0.0),
