@@ -436,13 +436,21 @@ def bench_c3(args):
     err = {k: float(np.abs(got[:, c] - ref[:, c]).max() / np.abs(ref[:, c]).max())
            for c, k in enumerate(["value", "d/dx", "d/dy", "d/dz"])}
     flops = 2 * 192 + 3 * 45  # contraction FMAs + basis/span work per sample (p = 3)
+    tflops = n * flops / (ev_ms * 1e-3) / 1e12
+    hbm = _roof(n * 28 + 4 * b.ctrl.size, ev_ms, "query", "c3")
     line = _common(args, "queried samples/sec (value+grad)", n / (ms * 1e-3), "samples/s", ms,
                    "f32",
                    "C3 ray-sample query: 1024^3 domain as 16^3 micro-models (NCP* per axis in "
                    "8..32, cubic), 1920x1080 rays x 512 samples (1.06e9 non-grid positions), "
                    "block lookup + span search + value + gradient, FP32",
-                   {"roofline": _roof(n * 28 + 4 * b.ctrl.size, ev_ms, "query", "c3"),
-                    "valu_tflops": n * flops / (ev_ms * 1e-3) / 1e12,
+                   {"roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
+                                 "frac_of_unpacked_fp32": tflops / VALU_UNPACKED_TFLOPS,
+                                 "traffic": hbm["traffic"], "kernel": "query",
+                                 "flops_per_sample": flops, "avg_launch_ms": ev_ms,
+                                 "hbm": {"achieved": hbm["achieved"], "unit": "GB/s",
+                                         "frac": hbm["frac"],
+                                         "alg_bytes_per_launch": hbm["alg_bytes_per_launch"]}},
                     "order": {k: {"ms_per_step": v[0], "avg_launch_ms": v[1]}
                               for k, v in orders.items()},
                     "timed_order": best,
@@ -506,6 +514,10 @@ def bench_c3(args):
 # ------------------------------------------------------------------ F1
 
 VALU_PEAK_TFLOPS = 157.3
+# the same vector ALUs without packed FP32 (one FMA per lane per clock):
+# 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz; the kernels here are built without
+# packed FP32 instructions, so this is the rate their FMAs can reach
+VALU_UNPACKED_TFLOPS = 78.6
 
 
 def bench_f1(args):
@@ -574,6 +586,7 @@ def bench_f1(args):
                    "FP32; early termination off",
                    {"roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS,
                                  "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS,
+                                 "frac_of_unpacked_fp32": tflops / VALU_UNPACKED_TFLOPS,
                                  "traffic": traffic_from_profiles("render", "f1"),
                                  "kernel": "render", "flops_per_sample": flops,
                                  "avg_launch_ms": ev_ms},
