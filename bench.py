@@ -991,7 +991,7 @@ def bench_c4(args):
         o, n = int(b.ctrl_off[k]), int(np.prod(b.ncp[k]))
         gerr = max(gerr, float(np.abs(grad[o:o + n] - G[o:o + n]).max() /
                                np.abs(G[o:o + n]).max()))
-    err = {"loss": abs(float(loss) - loss64) / loss64, "gradient": gerr,
+    err = {"loss": abs(float(loss.detach()) - loss64) / loss64, "gradient": gerr,
            "sample": "loss over all 256 blocks; gradient max |gpu - fp64| / max |fp64| per "
                      "block on 8 seeded blocks, at the lattice after the timed steps"}
     # the timed form: the eager iteration or its HIP-graph replay (the same
