@@ -107,7 +107,7 @@ def test_fused_mse_gradient_vs_oracle(fa, nblocks, resn):
     loss.backward()
     grad = ctrl.grad.detach().cpu().numpy().astype(np.float64)
     go, ga, lo, _, gs = _oracle_grad(b, P0, y, res)
-    assert abs(float(loss) - lo) <= 1e-5 * lo
+    assert abs(float(loss.detach()) - lo) <= 1e-5 * lo
     valid = np.zeros(b.ctrl.size, bool)
     for k in range(b.nblocks):
         o = int(b.ctrl_off[k])
