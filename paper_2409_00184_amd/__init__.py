@@ -782,7 +782,9 @@ class FAFitMSE(torch.autograd.Function):
     the cotangent.  y: [nblocks, *res] float32.  The adjoint writes into a
     buffer kept on `models` (zeroed once: the padding between blocks'
     lattices, which the adjoint leaves alone, stays zero); the gradient
-    returned is a new tensor, its product with the incoming gradient."""
+    returned is a new tensor, its product with the incoming gradient, so
+    only backward passes on one `models` that overlap on different streams
+    would share the buffer (run them on one stream)."""
 
     @staticmethod
     def forward(ctx, ctrl, models, res, y, plan):
