@@ -116,7 +116,7 @@ def test_fused_mse_gradient_vs_oracle(fa, nblocks, resn):
     lim = 256 * U32 * ga[valid] + 64 * U32 * gs[valid] + 1e-30
     assert np.all(err <= lim), float((err / lim).max())
     _, g2, l2 = _fit_case(fa, b, y, P0, res)
-    assert abs(float(loss) - l2) <= 1e-5 * l2
+    assert abs(float(loss.detach()) - l2) <= 1e-5 * l2
     assert np.abs(grad - g2)[valid].max() <= 1e-5 * np.abs(g2[valid]).max()
 
 
@@ -306,6 +306,28 @@ def test_autotune_interleaved_layout(fa, tmp_path, monkeypatch):
     assert a.shape == (b.nblocks,) + res + (4,)
     assert torch.equal(a, fa.decode(m, res, mk))
     assert torch.equal(a, fa.decode(m, res, 15).permute(0, 2, 3, 4, 1))
+
+
+def test_fused_mse_backward_scale_and_fresh_gradients(fa):
+    """FAFitMSE's backward multiplies the adjoint (written into a buffer
+    kept on the micro-models) by the incoming gradient and returns a new
+    tensor each time: a second backward with the loss scaled by 3 gives
+    exactly 3x the first gradient, and neither gradient is the buffer."""
+    say("fused mse backward scale")
+    b = mixed_batch(68, 5, ncp_lo=4, ncp_hi=12)
+    m = models(b)
+    res = (9, 10, 12)
+    g = fi.rng(69)
+    y = torch.as_tensor(g.normal(size=(b.nblocks,) + res).astype(np.float32)).cuda()
+    P0 = torch.as_tensor(g.normal(size=b.ctrl.size).astype(np.float32)).cuda()
+    ctrl = P0.clone().requires_grad_(True)
+    (g1,) = torch.autograd.grad(fa.FAFitMSE.apply(ctrl, m, res, y, None), ctrl)
+    (g2,) = torch.autograd.grad(3.0 * fa.FAFitMSE.apply(ctrl, m, res, y, None), ctrl)
+    assert torch.equal(g2, g1 * 3.0)
+    buf = m._adjoint_buf
+    assert len({g1.data_ptr(), g2.data_ptr(), buf.data_ptr()}) == 3
+    # the buffer holds the unscaled adjoint of the last backward
+    assert torch.equal(buf, g1)
 
 
 @pytest.mark.parametrize("n", [1, 255, 256, 257, 5000])
