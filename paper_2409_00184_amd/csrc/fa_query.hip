@@ -67,7 +67,8 @@ __global__ __launch_bounds__(256) void query_kernel(QueryLaunch a) {
 // per micro-model a ray tile crosses).  Every window gather of the
 // evaluation then reads LDS instead of the vector L1; a wave with a sample
 // outside both slots (a third micro-model, or one larger than a slot) takes
-// the per-lane global form of eval_point for the step.  Positions and
+// the per-lane global form of eval_point for the step (FP32 lattices), or
+// serves its other micro-models one at a time (2-byte lattices).  Positions and
 // results stay coalesced: kLS consecutive samples of a ray are kLS * 12 and
 // kLS * 16 contiguous bytes.
 #ifndef FA_RAYS_WAVES
@@ -272,9 +273,32 @@ __global__ __launch_bounds__(64 * kLW) void query_rays_lds_kernel(QueryLaunch a)
             float4 res = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (__all(cur_blk < 0 || sl >= 0)) {
                 if (sl >= 0) res = eval_slot<DT>(sm, sl, cu);
-            } else if (cur_blk >= 0) {
-                const fa_block &Bd = a.blocks[cur_blk];
-                res = query_any<DT, false>(a, view_of(Bd), Bd.degree[0], cu);
+            } else if constexpr (DT == FA_F32) {
+                if (cur_blk >= 0) {
+                    const fa_block &Bd = a.blocks[cur_blk];
+                    res = query_any<DT, false>(a, view_of(Bd), Bd.degree[0], cu);
+                }
+            } else {
+                // 2-byte lattices: lanes whose micro-model is in a slot read
+                // it there; the wave's other micro-models are served one
+                // after the other through scalar descriptors, every lane
+                // taking part (the span search exchanges knots across lanes)
+                // and keeping the result of its own micro-model.  The
+                // per-lane form would need more than the 128 registers a
+                // 1024-thread workgroup allows.
+                if (sl >= 0) res = eval_slot<DT>(sm, sl, cu);
+                bool pend = cur_blk >= 0 && sl < 0;
+                while (__any(pend)) {
+                    const uint64_t pm = __ballot(pend);
+                    const int b0 = __builtin_amdgcn_readlane(cur_blk, (int)__builtin_ctzll(pm));
+                    const fa_block &B0 = a.blocks[b0];
+                    const float4 r =
+                        query_any<DT, true>(a, uniform_view_of(B0), uni(B0.degree[0]), cu);
+                    if (pend && cur_blk == b0) {
+                        res = r;
+                        pend = false;
+                    }
+                }
             }
             if (!cur_live) continue;
             res.y *= a.rscale[0];
