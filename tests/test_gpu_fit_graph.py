@@ -265,9 +265,9 @@ def test_captured_fit_step_matches_eager(fa, adam):
         le = eager()
         torch.cuda.synchronize()
         d = (cg.detach() - ce.detach()).abs().max().item()
-        say("  replay", rep, "loss", float(loss_g), float(le), "max |ctrl diff|", d)
+        say("  replay", rep, "loss", float(loss_g.detach()), float(le.detach()), "max |ctrl diff|", d)
         assert torch.equal(cg.detach(), ce.detach()), ("ctrl", rep, d)
-        assert float(loss_g) == float(le), ("loss", rep)
+        assert float(loss_g.detach()) == float(le.detach()), ("loss", rep)
         _ = (ce.detach() * 2).sum().item()  # eager work between replays
 
 
